@@ -1,0 +1,208 @@
+"""Seeded synthetic workloads shaped like the paper's test problems.
+
+This module holds only input recipes: seeded initial fields (rho, u, theta)
+and the run parameters of each workload.  It contains none of the lattice
+Boltzmann arithmetic, so the GPU library and the FP64 oracle can both consume
+it without sharing any of the method.  Fields are generated in FP64, rounded
+to FP32, and returned as float32 numpy arrays in the layout
+rho[nz, ny, nx] (or [ny, nx]), u[D, ...], theta[...].
+
+Each workload returns a dict with
+  "config": plain dict of run parameters (the same keys as the C config),
+  "rho", "u", "theta": float32 arrays,
+  "steps": the horizon the workload is quoted on,
+  "name": a short workload name.
+"""
+import math
+
+import numpy as np
+
+D2Q37 = 0
+D3Q39 = 1
+SRC_BODY = 1
+SRC_THERMAL = 2
+SRC_PTENSOR = 4
+
+# Lattice constants used only to express input parameters (a background flow
+# at a given Mach number, a viscosity as tau).  c0^2 of D2Q37 is the root of
+# its isotropy equations (Section 4.1, c0 ~ 0.83543); D3Q39 has c0^2 = 2/3.
+C0SQ_D2Q37 = 0.6979533220196833
+C0SQ_D3Q39 = 2.0 / 3.0
+
+# Maxwell-construction coexistence densities of the van der Waals gas
+# (a = 9/49, b = 2/21) at T = 0.85 Tc; checked against the oracle's own
+# equal-area solve in the tests.
+VDW_A = 9.0 / 49.0
+VDW_B = 2.0 / 21.0
+VDW_TC = 8.0 * VDW_A / (27.0 * VDW_B)
+VDW_RHO_L_085 = 6.3249911456774175
+VDW_RHO_G_085 = 1.1190548758159977
+
+
+def base_config(**kw):
+    cfg = dict(lattice=D2Q37, nx=1, ny=1, nz=1, tau_hat=0.8, sources=0, isothermal=0,
+               g=(0.0, 0.0, 0.0), prandtl=1.0, eos_a=0.0, eos_b=0.0, eos_T=0.0, sc_G=-1.0,
+               ptensor_k=0.0, walls=0, theta_wall=(1.0, 1.0),
+               u_wall=((0.0, 0.0, 0.0), (0.0, 0.0, 0.0)), rho0=1.0, theta0=1.0,
+               u0=(0.0, 0.0, 0.0))
+    cfg.update(kw)
+    return cfg
+
+
+def _f32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64).astype(np.float32))
+
+
+def body_force_2d(n=64, steps=500, seed=1, tau_hat=0.8, g_y=1e-5, amp_rho=0.01, amp_u=0.05):
+    """D2Q37 + body force, n x n periodic: rho = 1 + 0.01 N(0,1), u_x = 0.05 sin(2 pi y/n)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    rho = 1.0 + amp_rho * rng.standard_normal((n, n))
+    y = np.arange(n)[:, None] * np.ones((1, n))
+    u = np.zeros((2, n, n))
+    u[0] = amp_u * np.sin(2 * math.pi * y / n)
+    theta = np.ones((n, n))
+    cfg = base_config(lattice=D2Q37, nx=n, ny=n, tau_hat=tau_hat, sources=SRC_BODY,
+                      g=(0.0, g_y, 0.0), rho0=1.0)
+    return dict(name="d2q37_body_%d" % n, config=cfg, rho=_f32(rho), u=_f32(u), theta=_f32(theta),
+                steps=steps)
+
+
+def thermal_2d(n=1024, steps=20000, seed=2, tau_hat=0.8, prandtl=0.71, mach=0.3, amp=0.05):
+    """D2Q37 + thermal source, n x n periodic: background u_x = Ma c0, a shear
+    wave in u_y and a pressure-balanced entropy wave theta = 1 + amp sin(.),
+    rho = 1/theta, with seeded phases."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ph1, ph2 = rng.uniform(0.0, 2 * math.pi, size=2)
+    x = np.ones((n, 1)) * np.arange(n)[None, :]
+    U0 = mach * math.sqrt(C0SQ_D2Q37)
+    u = np.zeros((2, n, n))
+    u[0] = U0
+    u[1] = amp * np.sin(2 * math.pi * x / n + ph1)
+    theta = 1.0 + amp * np.sin(2 * math.pi * x / n + ph2)
+    rho = 1.0 / theta
+    cfg = base_config(lattice=D2Q37, nx=n, ny=n, tau_hat=tau_hat, sources=SRC_THERMAL,
+                      prandtl=prandtl, rho0=1.0, u0=(U0, 0.0, 0.0))
+    return dict(name="d2q37_thermal_%d" % n, config=cfg, rho=_f32(rho), u=_f32(u),
+                theta=_f32(theta), steps=steps)
+
+
+def _place_droplets(rng, n, ndrops, rmin, rmax, gap, max_tries=200000):
+    """Non-overlapping droplets (periodic distance >= r1 + r2 + gap) by rejection."""
+    drops = []
+    tries = 0
+    while len(drops) < ndrops and tries < max_tries:
+        tries += 1
+        r = rng.uniform(rmin, rmax)
+        cx, cy = rng.uniform(0, n, size=2)
+        ok = True
+        for (px, py, pr) in drops:
+            dx = abs(cx - px); dx = min(dx, n - dx)
+            dy = abs(cy - py); dy = min(dy, n - dy)
+            if math.hypot(dx, dy) < r + pr + gap:
+                ok = False
+                break
+        if ok:
+            drops.append((cx, cy, r))
+    return drops
+
+
+def droplet_profile(n, drops, rho_l, rho_g, width=5.0):
+    """Superposed droplet profiles of Eq. (5.11) on an n x n periodic grid."""
+    y, x = np.mgrid[0:n, 0:n].astype(np.float64)
+    rho = np.full((n, n), rho_g)
+    for (cx, cy, r) in drops:
+        dx = np.abs(x - cx); dx = np.minimum(dx, n - dx)
+        dy = np.abs(y - cy); dy = np.minimum(dy, n - dy)
+        d = np.hypot(dx, dy)
+        rho += 0.5 * (rho_l - rho_g) * (1.0 - np.tanh(2.0 * (d - r) / width))
+    return rho
+
+
+def ptensor_2d(n=2048, steps=1000, seed=3, ndrops=100, rmin=20.0, rmax=80.0, gap=10.0, nu=0.2,
+               t_reduced=0.85, k=3.02, rho_l=VDW_RHO_L_085, rho_g=VDW_RHO_G_085, width=5.0):
+    """D2Q37 + pseudopotential force + pressure-tensor source, van der Waals
+    EOS, isothermal, n x n periodic with seeded random droplets (Eq. 5.11)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    drops = _place_droplets(rng, n, ndrops, rmin, rmax, gap)
+    rho = droplet_profile(n, drops, rho_l, rho_g, width)
+    u = np.zeros((2, n, n))
+    theta = np.ones((n, n))
+    tau_hat = 0.5 + nu / C0SQ_D2Q37
+    rho0 = float(rho.mean())
+    cfg = base_config(lattice=D2Q37, nx=n, ny=n, tau_hat=tau_hat, sources=SRC_PTENSOR, isothermal=1,
+                      eos_a=VDW_A, eos_b=VDW_B, eos_T=t_reduced * VDW_TC, sc_G=-1.0, ptensor_k=k,
+                      rho0=rho0)
+    return dict(name="d2q37_ptensor_%d" % n, config=cfg, rho=_f32(rho), u=_f32(u),
+                theta=_f32(theta), steps=steps, drops=drops)
+
+
+def single_droplet_2d(n, radius, nu=0.2, t_reduced=0.85, k=3.02, rho_l=VDW_RHO_L_085,
+                      rho_g=VDW_RHO_G_085, width=5.0, steps=2000):
+    """One centred droplet of Eq. (5.11) on an n x n periodic grid."""
+    rho = droplet_profile(n, [(n / 2.0, n / 2.0, radius)], rho_l, rho_g, width)
+    tau_hat = 0.5 + nu / C0SQ_D2Q37
+    cfg = base_config(lattice=D2Q37, nx=n, ny=n, tau_hat=tau_hat, sources=SRC_PTENSOR, isothermal=1,
+                      eos_a=VDW_A, eos_b=VDW_B, eos_T=t_reduced * VDW_TC, sc_G=-1.0, ptensor_k=k,
+                      rho0=float(rho.mean()))
+    return dict(name="d2q37_droplet_%d_r%g" % (n, radius), config=cfg, rho=_f32(rho),
+                u=_f32(np.zeros((2, n, n))), theta=_f32(np.ones((n, n))), steps=steps)
+
+
+def rayleigh_benard_3d(n=256, steps=200, seed=4, ra=1e5, prandtl=0.71, nu=0.04, theta_hot=1.4,
+                       theta_cold=1.0, noise=1e-3, rho_mean_theta=1.2, walls=1, nz=None):
+    """D3Q39 + body force + thermal source: an n x n x nz box heated from below
+    (walls normal to z, hot at z = 0), periodic in x and y.  g follows the
+    Rayleigh number definition of Eq. (5.6) with fluid height H = nz - 2 (one
+    wall-node layer per side); theta is the linear conduction profile plus
+    seeded noise, rho = 1.2 / theta, u = 0."""
+    nz = n if nz is None else nz
+    rng = np.random.Generator(np.random.PCG64(seed))
+    H = nz - 2 if walls else nz
+    g = ra * nu * nu * (theta_hot + theta_cold) / (2.0 * prandtl * (theta_hot - theta_cold) * H ** 3)
+    z = np.arange(nz, dtype=np.float64)[:, None, None] * np.ones((1, n, n))
+    theta = theta_hot - (theta_hot - theta_cold) * (z - 0.5) / H
+    theta = theta + noise * rng.standard_normal((nz, n, n))
+    rho = rho_mean_theta / theta
+    u = np.zeros((3, nz, n, n))
+    tau_hat = 0.5 + nu / C0SQ_D3Q39
+    cfg = base_config(lattice=D3Q39, nx=n, ny=n, nz=nz, tau_hat=tau_hat,
+                      sources=SRC_BODY | SRC_THERMAL, g=(0.0, 0.0, -g), prandtl=prandtl,
+                      walls=walls, theta_wall=(theta_hot, theta_cold), rho0=1.0,
+                      theta0=0.5 * (theta_hot + theta_cold))
+    return dict(name="d3q39_rb_%dx%dx%d" % (n, n, nz), config=cfg, rho=_f32(rho), u=_f32(u),
+                theta=_f32(theta), steps=steps)
+
+
+def batched_runs(nruns=512, seed=5, nmin=32, nmax=256, steps=500):
+    """Independent D2Q37 body-force + thermal runs of uneven sizes and
+    parameters; run r draws from seed + r: n ~ U{nmin..nmax}, tau ~ U[0.6, 1.2],
+    Pr ~ U[0.5, 2], g_y ~ U[0, 1e-5]; fields as the body-force workload plus
+    theta = 1 + 0.05 sin(2 pi x/n + phase)."""
+    runs = []
+    for r in range(nruns):
+        rng = np.random.Generator(np.random.PCG64(seed + r))
+        n = int(rng.integers(nmin, nmax + 1))
+        tau_hat = float(rng.uniform(0.6, 1.2))
+        pr = float(rng.uniform(0.5, 2.0))
+        gy = float(rng.uniform(0.0, 1e-5))
+        ph = float(rng.uniform(0.0, 2 * math.pi))
+        rho = 1.0 + 0.01 * rng.standard_normal((n, n))
+        y, x = np.mgrid[0:n, 0:n].astype(np.float64)
+        u = np.zeros((2, n, n))
+        u[0] = 0.05 * np.sin(2 * math.pi * y / n)
+        theta = 1.0 + 0.05 * np.sin(2 * math.pi * x / n + ph)
+        cfg = base_config(lattice=D2Q37, nx=n, ny=n, tau_hat=tau_hat,
+                          sources=SRC_BODY | SRC_THERMAL, g=(0.0, gy, 0.0), prandtl=pr)
+        runs.append(dict(name="run%d_n%d" % (r, n), config=cfg, rho=_f32(rho), u=_f32(u),
+                         theta=_f32(theta), steps=steps))
+    return runs
+
+
+def uniform_fields(shape, D, rho=1.0, u=(0.0, 0.0, 0.0), theta=1.0):
+    """Uniform rest-state (or uniform-flow) fields of a given grid shape."""
+    r = np.full(shape, rho)
+    uu = np.zeros((D,) + tuple(shape))
+    for a in range(D):
+        uu[a] = u[a]
+    t = np.full(shape, theta)
+    return _f32(r), _f32(uu), _f32(t)

@@ -1,0 +1,185 @@
+/*
+ * holb.h -- C ABI of the high-order lattice Boltzmann library for AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The library advances the shifted BGK lattice Boltzmann equation with
+ * Hermite-polynomial source terms of Li et al., "Constructing the body
+ * source for high-order lattice Boltzmann method" (arXiv:2411.10751):
+ *
+ *   f^_i(x + c_i, t + 1) - f^_i(x, t) = -(f^_i - f^eq_i) / tau_hat
+ *                                      + (1 - 1 / (2 tau_hat)) S_i     (Eq. 4.4)
+ *
+ * on the D2Q37 or D3Q39 multispeed lattice (Section 4.1), with the
+ * fourth-order Hermite equilibrium f^eq (Eq. 2.2) and the source
+ * S_i = F_i + H_i + P_i made of the body force (Eq. 3.3), the thermal-
+ * dissipation correction that sets the Prandtl number (Eq. 3.7) and the
+ * pressure-tensor source of the pseudopotential multiphase model (Eqs. 3.8,
+ * 3.12).  Macroscopic fields follow the shifted moments of Eq. (4.5).
+ *
+ * Conventions
+ *  - Lattice units: dt = dx = 1.  Velocities u are lattice velocities
+ *    (Table 2 form); temperature theta is 1 at the lattice reference
+ *    temperature, so the isothermal sound speed squared is c0^2 theta.
+ *  - Fields are structure-of-arrays in device memory, float32:
+ *    rho[N], u[D][N], theta[N], with cell = x + nx * (y + ny * z),
+ *    N = nx * ny * nz (nz = 1 for D2Q37).
+ *  - Every call returns a holb_status; no exception crosses the ABI.  On
+ *    failure holb_last_error() returns a thread-local message.
+ *  - Ownership: the caller allocates all device memory (the workspace and
+ *    every field buffer) and keeps it alive until *_destroy; the library
+ *    allocates none.  Handles are host objects freed by *_destroy.
+ *  - Streams: all GPU work of a handle is ordered on the HIP stream given at
+ *    creation (NULL = the default stream).  One handle must not be used from
+ *    two threads at once.
+ */
+#ifndef HOLB_H
+#define HOLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HOLB_ABI_VERSION 1
+
+typedef int32_t holb_status;
+#define HOLB_OK 0
+#define HOLB_EINVAL (-1)       /* bad argument or configuration value */
+#define HOLB_ESIZE (-2)        /* buffer or workspace too small / misaligned */
+#define HOLB_EHIP (-3)         /* a HIP runtime call failed */
+#define HOLB_ENUMERIC (-4)     /* the device raised a numeric error (see holb_error_flags) */
+#define HOLB_EUNSUPPORTED (-5) /* valid values, combination not supported */
+#define HOLB_ESTATE (-6)       /* call out of order (e.g. step before init) */
+
+/* Lattices (Section 4.1). */
+#define HOLB_D2Q37 0
+#define HOLB_D3Q39 1
+
+/* Source-term mask. */
+#define HOLB_SRC_BODY 1u    /* body force F = rho g, Eq. (3.3) */
+#define HOLB_SRC_THERMAL 2u /* thermal-dissipation source H_i, Eq. (3.7) */
+#define HOLB_SRC_PTENSOR 4u /* pseudopotential force (Eq. 3.8) + P_i (Eq. 3.12) */
+
+/* Population storage in device memory.  Arithmetic is always FP32.  The
+ * 16-bit forms store q_i = (f_i - f^eq_i(rho0, u0, theta0)) / w_i, rounded to
+ * nearest-even, and decode f_i = w_i (q_i + f^eq_i(ref) / w_i). */
+#define HOLB_STORE_F32 0
+#define HOLB_STORE_F16DEV 1
+#define HOLB_STORE_BF16DEV 2
+
+/* Device error flags (holb_error_flags). */
+#define HOLB_ERR_DENSITY 1u  /* rho <= 0 or not finite */
+#define HOLB_ERR_THETA 2u    /* theta <= 0 or not finite */
+#define HOLB_ERR_EOS 4u      /* psi^2 < 0 or b rho >= 1 in the equation of state */
+
+typedef struct {
+    int32_t abi_version;  /* must equal HOLB_ABI_VERSION */
+    int32_t lattice;      /* HOLB_D2Q37 or HOLB_D3Q39 */
+    int32_t nx, ny, nz;   /* grid; nz = 1 for D2Q37 */
+    double tau_hat;       /* shifted relaxation time, > 0.5 (Eq. 4.3); nu = c0^2 theta (tau_hat - 1/2) */
+    uint32_t sources;     /* HOLB_SRC_* mask */
+    int32_t isothermal;   /* 1: theta held at 1 (multiphase mode of Section 5.4) */
+    double g[3];          /* body-force acceleration, F = rho g (HOLB_SRC_BODY) */
+    double prandtl;       /* Prandtl number of H_i (HOLB_SRC_THERMAL), > 0 */
+    double eos_a, eos_b, eos_T; /* van der Waals p = rho T / (1 - b rho) - a rho^2 */
+    double sc_G;          /* pseudopotential coupling G (the paper uses -1) */
+    double ptensor_k;     /* free parameter k of P_i, Eq. (3.12) */
+    int32_t storage;      /* HOLB_STORE_* */
+    double rho0, theta0, u0[3]; /* reference state of the 16-bit deviation storage */
+    int32_t walls;        /* 0: periodic; 1: TMS walls (Eqs. 4.7-4.8) normal to the last axis */
+    double theta_wall[2]; /* wall temperatures: [0] at index 0, [1] at index n-1 */
+    double u_wall[2][3];  /* wall velocities, same order */
+} holb_config;
+
+typedef struct holb_sim holb_sim;
+typedef struct holb_batch holb_batch;
+
+/* Thread-local description of the last failure in this thread. */
+const char* holb_last_error(void);
+
+/* Velocity set used by the library (Section 4.1): Q, D, c[Q][3] (int),
+ * w[Q], c0^2.  Any output pointer may be NULL.  c/w need room for 39. */
+holb_status holb_lattice_info(int32_t lattice, int32_t* Q, int32_t* D, int32_t* c, double* w,
+                              double* c0sq);
+
+/* Bytes of device workspace a configuration needs (two population buffers,
+ * stencil fields, wall targets, reduction partials).  Pure host call. */
+holb_status holb_workspace_size(const holb_config* cfg, size_t* bytes);
+
+/* Validate cfg and bind a caller-owned device workspace (256-byte aligned,
+ * at least holb_workspace_size bytes) and stream.  Pure host call: launches
+ * nothing.  Errors: HOLB_EINVAL (values, tau_hat <= 0.5, dims), HOLB_ESIZE
+ * (workspace), HOLB_EUNSUPPORTED (e.g. thermal source with isothermal=1,
+ * pressure tensor without isothermal=1 or with walls). */
+holb_status holb_create(const holb_config* cfg, void* dev_workspace, size_t bytes, void* hip_stream,
+                        holb_sim** out);
+
+/* Set the initial state f^0 = f^eq(rho, u, theta) from device fields
+ * (rho[N], u[D][N], theta[N]; theta ignored when isothermal).  The first
+ * holb_step then performs the t = 0 collision with the source terms.
+ * Asynchronous. */
+holb_status holb_init(holb_sim* s, const float* rho, const float* u, const float* theta);
+
+/* Advance n >= 0 time steps of Eq. (4.4) (wall closure, shifted moments,
+ * sources, BGK collision, streaming).  Asynchronous on the stream. */
+holb_status holb_step(holb_sim* s, int64_t n);
+
+/* Macroscopic fields of the current state (Eq. 4.5) into device buffers
+ * rho[N], u[D][N], theta[N] (any may be NULL).  Synchronises the stream and
+ * returns HOLB_ENUMERIC if the device error flags are set. */
+holb_status holb_fields(holb_sim* s, float* rho, float* u, float* theta);
+
+/* Global FP64 totals of the current state into host out[5]: mass sum rho,
+ * momentum sum rho u (x, y, z; z = 0 in 2D), energy
+ * sum (rho |u|^2 + rho D c0^2 theta) / 2.  Deterministic order.  Synchronises;
+ * returns HOLB_ENUMERIC if the device error flags are set. */
+holb_status holb_reduce(holb_sim* s, double out[5]);
+
+/* Device error flags (HOLB_ERR_*) raised since creation; synchronises. */
+holb_status holb_error_flags(holb_sim* s, uint32_t* flags);
+
+/* Raw population state: size in bytes, and device-to-device copies out of /
+ * into the library's current buffer (layout: Q planes of 256-byte aligned
+ * pitch, element type per storage, velocity order of holb_lattice_info; the
+ * buffer holds the post-collision populations of the last step, so that
+ * pulling f^(x) = buf[i][x - c_i] gives the current pre-collision state). */
+holb_status holb_state_bytes(holb_sim* s, size_t* bytes);
+holb_status holb_get_state(holb_sim* s, void* dev_dst, size_t bytes);
+holb_status holb_set_state(holb_sim* s, const void* dev_src, size_t bytes);
+
+/* Pick the fastest kernel variant for this configuration by timing each
+ * candidate on trial steps that leave the state untouched; results are
+ * bitwise identical across variants.  Synchronises.  variant_out may be NULL. */
+holb_status holb_tune(holb_sim* s, int32_t* variant_out);
+/* Force a kernel variant (0 = the default); HOLB_EUNSUPPORTED if it does not
+ * apply to this configuration.  holb_num_variants reports how many exist. */
+holb_status holb_set_variant(holb_sim* s, int32_t variant);
+holb_status holb_num_variants(holb_sim* s, int32_t* n);
+
+holb_status holb_destroy(holb_sim* s);
+
+/* ---- Batched form: many independent periodic D2Q37 runs in one launch ---- */
+
+/* Every run uses its own grid (nx, ny), tau_hat, sources, g and Pr; all runs
+ * share lattice (D2Q37), storage (HOLB_STORE_F32), isothermal = 0 and
+ * walls = 0. */
+holb_status holb_batch_workspace_size(const holb_config* cfgs, int32_t n_runs, size_t* bytes);
+holb_status holb_batch_create(const holb_config* cfgs, int32_t n_runs, void* dev_workspace,
+                              size_t bytes, void* hip_stream, holb_batch** out);
+/* rho/u/theta: host arrays of n_runs device pointers, fields laid out per run. */
+holb_status holb_batch_init(holb_batch* b, const float* const* rho, const float* const* u,
+                            const float* const* theta);
+/* n steps of every run; steps are replayed from a captured HIP graph. */
+holb_status holb_batch_step(holb_batch* b, int64_t n);
+holb_status holb_batch_fields(holb_batch* b, int32_t run, float* rho, float* u, float* theta);
+holb_status holb_batch_reduce(holb_batch* b, int32_t run, double out[5]);
+holb_status holb_batch_tune(holb_batch* b, int32_t* variant_out);
+holb_status holb_batch_set_variant(holb_batch* b, int32_t variant);
+holb_status holb_batch_destroy(holb_batch* b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HOLB_H */

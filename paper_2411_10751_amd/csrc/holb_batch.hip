@@ -1,0 +1,419 @@
+// Batched form: many independent periodic D2Q37 runs of uneven sizes and
+// parameters advanced together.  All runs live in one workspace; a device
+// run table holds each run's grid, offsets and parameters, and a work list
+// splits every run into fixed-size items.  One persistent launch per pass
+// walks the work list with a grid stride, and the step loop is captured once
+// into a HIP graph that is replayed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "holb_cell.h"
+#include "holb_host.h"
+#include "holb_internal.h"
+#include "holb_march.h"
+
+using namespace holb;
+
+namespace holb {
+
+struct RunDesc {
+    int nx, ny, N;
+    unsigned flags;
+    long long off;     // element offset of the run's planes in a population buffer
+    long long pitch;   // elements per population plane of this run
+    long long cell0;   // offset of the run's cells in the theta field
+    float omega, kappa, g0, g1, hfac;
+    int pad;
+};
+
+constexpr int BATCH_ITEM = 256;
+
+__device__ __forceinline__ KParams run_params(const RunDesc& r, unsigned* err)
+{
+    KParams p = {};
+    p.nx = r.nx; p.ny = r.ny; p.nz = 1;
+    p.walls = 0;
+    p.N = r.N;
+    p.nlayer = r.nx;
+    p.pitch = r.pitch;
+    p.flags = r.flags;
+    p.omega = r.omega; p.kappa = r.kappa;
+    p.g[0] = r.g0; p.g[1] = r.g1; p.g[2] = 0.f;
+    p.hfac = r.hfac;
+    p.err = err;
+    return p;
+}
+
+template <int FAM>
+__global__ void __launch_bounds__(BATCH_ITEM)
+k_batch_aux(const RunDesc* __restrict__ runs, const int2* __restrict__ items, int nitems,
+            const float* __restrict__ fin, float* __restrict__ aux, const float* __restrict__ tgi, unsigned* err)
+{
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int2 t = items[it];
+        const RunDesc r = runs[t.x];
+        const int cell = t.y + threadIdx.x;
+        if (cell < r.N) {
+            const KParams p = run_params(r, err);
+            aux_cell<D2Q37, ST_F32, FAM>(p, fin + r.off, tgi, aux + r.cell0, nullptr, cell);
+        }
+    }
+}
+
+template <int FAM>
+__global__ void __launch_bounds__(BATCH_ITEM)
+k_batch_step(const RunDesc* __restrict__ runs, const int2* __restrict__ items, int nitems,
+             const float* __restrict__ fin, float* __restrict__ fout, const float* __restrict__ aux,
+             const double* __restrict__ auxd, const float* __restrict__ tgi, float* __restrict__ tgo, unsigned* err)
+{
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int2 t = items[it];
+        const RunDesc r = runs[t.x];
+        const int cell = t.y + threadIdx.x;
+        if (cell < r.N) {
+            const KParams p = run_params(r, err);
+            step_cell<D2Q37, ST_F32, FAM>(p, fin + r.off, fout + r.off, aux + r.cell0, auxd, tgi, tgo, cell);
+        }
+    }
+}
+
+}  // namespace holb
+
+struct holb_batch {
+    std::vector<holb_config> cfgs;
+    std::vector<RunDesc> runs;
+    std::vector<int2> items;
+    int n = 0;
+    int fam = FAM_LOCAL;
+    char* ws = nullptr;
+    hipStream_t stream = nullptr;
+    size_t pop_off[2] = {0, 0}, pop_elems = 0, aux_off = 0, desc_off = 0, items_off = 0;
+    size_t part_off = 0, out_off = 0, err_off = 0, total = 0;
+    int max_partials = 0;
+    int cur = 0;
+    bool initialized = false;
+    int variant = 0;
+    hipStream_t cap = nullptr;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+
+    void drop_graphs()
+    {
+        for (int k = 0; k < 2; ++k)
+            if (graph[k]) {
+                (void)hipGraphExecDestroy(graph[k]);
+                graph[k] = nullptr;
+            }
+    }
+    ~holb_batch()
+    {
+        drop_graphs();
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+
+    const RunDesc* d_runs() const { return (const RunDesc*)(ws + desc_off); }
+    const int2* d_items() const { return (const int2*)(ws + items_off); }
+    float* pop(int k) const { return (float*)(ws + pop_off[k]); }
+    float* aux() const { return (float*)(ws + aux_off); }
+    unsigned* err() const { return (unsigned*)(ws + err_off); }
+
+    // persistent grid: a few blocks per compute unit, walking the work list
+    int grid() const
+    {
+        const int per_cu = variant == 2 ? 8 : 4;
+        return std::max(1, std::min((int)items.size(), 256 * per_cu));
+    }
+
+    hipError_t step_once(hipStream_t s, int from) const
+    {
+        const int nit = (int)items.size();
+        const float* fin = pop(from);
+        float* fout = pop(1 - from);
+        if (fam == FAM_THERMAL) {
+            hipLaunchKernelGGL(k_batch_aux<FAM_THERMAL>, dim3(grid()), dim3(BATCH_ITEM), 0, s, d_runs(), d_items(),
+                               nit, fin, aux(), (const float*)nullptr, err());
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k_batch_step<FAM_THERMAL>, dim3(grid()), dim3(BATCH_ITEM), 0, s, d_runs(),
+                               d_items(), nit, fin, fout, (const float*)aux(), (const double*)nullptr,
+                               (const float*)nullptr, (float*)nullptr, err());
+        } else {
+            hipLaunchKernelGGL(k_batch_step<FAM_LOCAL>, dim3(grid()), dim3(BATCH_ITEM), 0, s, d_runs(), d_items(),
+                               nit, fin, fout, (const float*)aux(), (const double*)nullptr, (const float*)nullptr,
+                               (float*)nullptr, err());
+        }
+        return hipGetLastError();
+    }
+
+    LaunchCtx run_ctx(int r) const
+    {
+        LaunchCtx c;
+        memset(&c, 0, sizeof c);
+        c.lattice = HOLB_D2Q37;
+        c.storage = ST_F32;
+        c.family = fam;
+        c.kp = params_of(&cfgs[r]);
+        c.kp.pitch = runs[r].pitch;
+        c.kp.err = err();
+        c.pop_in = pop(cur) + runs[r].off;
+        c.pop_out = pop(1 - cur) + runs[r].off;
+        c.aux_f = aux() + runs[r].cell0;
+        c.partials = (double*)(ws + part_off);
+        c.max_partials = max_partials;
+        c.stream = stream;
+        return c;
+    }
+};
+
+namespace {
+
+holb_status validate_batch(const holb_config* cfgs, int32_t n)
+{
+    if (!cfgs || n < 1) return fail(HOLB_EINVAL, "need at least one run");
+    for (int r = 0; r < n; ++r) {
+        holb_status s = validate(&cfgs[r]);
+        if (s) return fail(s, "run %d: %s", r, g_last_error.c_str());
+        const holb_config& c = cfgs[r];
+        if (c.lattice != HOLB_D2Q37 || c.storage != HOLB_STORE_F32 || c.isothermal || c.walls)
+            return fail(HOLB_EUNSUPPORTED, "run %d: batches hold periodic, non-isothermal D2Q37 FP32 runs", r);
+        if (c.sources & HOLB_SRC_PTENSOR) return fail(HOLB_EUNSUPPORTED, "run %d: no pressure tensor in batches", r);
+        if (family_of(c.sources) != family_of(cfgs[0].sources))
+            return fail(HOLB_EUNSUPPORTED, "run %d: all runs must share the thermal source on/off", r);
+    }
+    return HOLB_OK;
+}
+
+void plan(holb_batch* b, const holb_config* cfgs, int n)
+{
+    b->n = n;
+    b->cfgs.assign(cfgs, cfgs + n);
+    b->fam = family_of(cfgs[0].sources);
+    b->runs.resize(n);
+    b->items.clear();
+    size_t elems = 0, cells = 0;
+    int maxblk = 0;
+    for (int r = 0; r < n; ++r) {
+        const holb_config& c = cfgs[r];
+        RunDesc& d = b->runs[r];
+        memset(&d, 0, sizeof d);
+        d.nx = c.nx; d.ny = c.ny; d.N = c.nx * c.ny;
+        const KParams p = params_of(&c);
+        d.flags = p.flags;
+        d.omega = p.omega; d.kappa = p.kappa; d.g0 = p.g[0]; d.g1 = p.g[1]; d.hfac = p.hfac;
+        d.pitch = (long long)align_up((size_t)d.N, 64);
+        d.off = (long long)elems;
+        d.cell0 = (long long)cells;
+        elems += (size_t)D2Q37::Q * d.pitch;
+        cells += align_up((size_t)d.N, 64);
+        for (int c0 = 0; c0 < d.N; c0 += BATCH_ITEM) b->items.push_back(make_int2(r, c0));
+        maxblk = std::max(maxblk, (d.N + 255) / 256);
+    }
+    b->pop_elems = elems;
+    size_t off = 0;
+    b->pop_off[0] = off; off = align_up(off + elems * 4);
+    b->pop_off[1] = off; off = align_up(off + elems * 4);
+    b->aux_off = off; off = align_up(off + cells * 4);
+    b->desc_off = off; off = align_up(off + (size_t)n * sizeof(RunDesc));
+    b->items_off = off; off = align_up(off + b->items.size() * sizeof(int2));
+    b->max_partials = maxblk;
+    b->part_off = off; off = align_up(off + (size_t)maxblk * 5 * sizeof(double));
+    b->out_off = off; off = align_up(off + 8 * sizeof(double));
+    b->err_off = off; off = align_up(off + sizeof(unsigned));
+    b->total = off;
+}
+
+holb_status batch_check_flags(holb_batch* b)
+{
+    unsigned flags = 0;
+    hipError_t e = hipMemcpyAsync(&flags, b->err(), sizeof flags, hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return hip_fail(e, "reading the error flags");
+    if (flags) return fail(HOLB_ENUMERIC, "device numeric error flags 0x%x", flags);
+    return HOLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+holb_status holb_batch_workspace_size(const holb_config* cfgs, int32_t n_runs, size_t* bytes)
+{
+    holb_status s = validate_batch(cfgs, n_runs);
+    if (s) return s;
+    if (!bytes) return fail(HOLB_EINVAL, "bytes is NULL");
+    holb_batch tmp;
+    plan(&tmp, cfgs, n_runs);
+    *bytes = tmp.total;
+    return HOLB_OK;
+}
+
+holb_status holb_batch_create(const holb_config* cfgs, int32_t n_runs, void* dev_workspace, size_t bytes,
+                              void* hip_stream, holb_batch** out)
+{
+    if (!out) return fail(HOLB_EINVAL, "out is NULL");
+    *out = nullptr;
+    holb_status s = validate_batch(cfgs, n_runs);
+    if (s) return s;
+    if (!dev_workspace) return fail(HOLB_EINVAL, "workspace is NULL");
+    if ((uintptr_t)dev_workspace % ALIGN) return fail(HOLB_ESIZE, "workspace must be 256-byte aligned");
+    holb_batch* b = new (std::nothrow) holb_batch();
+    if (!b) return fail(HOLB_EINVAL, "out of host memory");
+    plan(b, cfgs, n_runs);
+    if (bytes < b->total) {
+        size_t need = b->total;
+        delete b;
+        return fail(HOLB_ESIZE, "workspace has %zu bytes, needs %zu", bytes, need);
+    }
+    b->ws = (char*)dev_workspace;
+    b->stream = (hipStream_t)hip_stream;
+    // Upload the run table and work list (host copies live in the handle).
+    hipError_t e = hipMemcpyAsync(b->ws + b->desc_off, b->runs.data(), b->runs.size() * sizeof(RunDesc),
+                                  hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->ws + b->items_off, b->items.data(), b->items.size() * sizeof(int2),
+                           hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(b->err(), 0, sizeof(unsigned), b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete b;
+        return hip_fail(e, "uploading the run table");
+    }
+    *out = b;
+    return HOLB_OK;
+}
+
+holb_status holb_batch_init(holb_batch* b, const float* const* rho, const float* const* u,
+                            const float* const* theta)
+{
+    if (!b || !rho || !u || !theta) return fail(HOLB_EINVAL, "NULL argument");
+    for (int r = 0; r < b->n; ++r) {
+        if (!rho[r] || !u[r] || !theta[r]) return fail(HOLB_EINVAL, "run %d: NULL field", r);
+        LaunchCtx c = b->run_ctx(r);
+        c.pop_out = b->pop(b->cur) + b->runs[r].off;
+        hipError_t e = launch_init(c, rho[r], u[r], theta[r]);
+        if (e != hipSuccess) return hip_fail(e, "batched init");
+    }
+    b->initialized = true;
+    return HOLB_OK;
+}
+
+static holb_status ensure_graph(holb_batch* b, int from)
+{
+    if (b->graph[from]) return HOLB_OK;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    hipError_t e1 = b->step_once(b->cap, from);
+    hipError_t e2 = e1 == hipSuccess ? b->step_once(b->cap, 1 - from) : e1;
+    e = hipStreamEndCapture(b->cap, &g);
+    if (e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_fail(e2, "capturing the step loop");
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&b->graph[from], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        b->graph[from] = nullptr;
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    return HOLB_OK;
+}
+
+holb_status holb_batch_step(holb_batch* b, int64_t n)
+{
+    if (!b) return fail(HOLB_EINVAL, "handle is NULL");
+    if (n < 0) return fail(HOLB_EINVAL, "n must be >= 0");
+    if (!b->initialized) return fail(HOLB_ESTATE, "holb_batch_step before holb_batch_init");
+    if (n >= 2) {
+        holb_status s = ensure_graph(b, b->cur);
+        if (s) return s;
+        for (int64_t k = 0; k + 1 < n; k += 2) {
+            hipError_t e = hipGraphLaunch(b->graph[b->cur], b->stream);
+            if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+        }
+    }
+    if (n % 2) {
+        hipError_t e = b->step_once(b->stream, b->cur);
+        if (e != hipSuccess) return hip_fail(e, "batched step");
+        b->cur = 1 - b->cur;
+    }
+    return HOLB_OK;
+}
+
+holb_status holb_batch_fields(holb_batch* b, int32_t run, float* rho, float* u, float* theta)
+{
+    if (!b) return fail(HOLB_EINVAL, "handle is NULL");
+    if (run < 0 || run >= b->n) return fail(HOLB_EINVAL, "run %d out of range", run);
+    if (!b->initialized) return fail(HOLB_ESTATE, "fields before init");
+    hipError_t e = launch_fields(b->run_ctx(run), rho, u, theta);
+    if (e != hipSuccess) return hip_fail(e, "batched fields");
+    return batch_check_flags(b);
+}
+
+holb_status holb_batch_reduce(holb_batch* b, int32_t run, double out[5])
+{
+    if (!b || !out) return fail(HOLB_EINVAL, "NULL argument");
+    if (run < 0 || run >= b->n) return fail(HOLB_EINVAL, "run %d out of range", run);
+    if (!b->initialized) return fail(HOLB_ESTATE, "reduce before init");
+    double* dout = (double*)(b->ws + b->out_off);
+    hipError_t e = launch_reduce(b->run_ctx(run), dout);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, dout, 5 * sizeof(double), hipMemcpyDeviceToHost, b->stream);
+    if (e != hipSuccess) return hip_fail(e, "batched reduce");
+    return batch_check_flags(b);
+}
+
+static const int BATCH_VARIANTS = 3;  // 0: 4 blocks/CU, 1: reserved, 2: 8 blocks/CU
+
+holb_status holb_batch_set_variant(holb_batch* b, int32_t variant)
+{
+    if (!b) return fail(HOLB_EINVAL, "handle is NULL");
+    if (variant != 0 && variant != 2) return fail(HOLB_EUNSUPPORTED, "variant %d not available", variant);
+    if (variant != b->variant) b->drop_graphs();
+    b->variant = variant;
+    return HOLB_OK;
+}
+
+holb_status holb_batch_tune(holb_batch* b, int32_t* variant_out)
+{
+    if (!b) return fail(HOLB_EINVAL, "handle is NULL");
+    if (!b->initialized) return fail(HOLB_ESTATE, "tune before init");
+    hipEvent_t t0, t1;
+    hipError_t e = hipEventCreate(&t0);
+    if (e == hipSuccess) e = hipEventCreate(&t1);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    const int keep = b->variant;
+    int best = keep;
+    float best_ms = 1e30f;
+    for (int v = 0; v < BATCH_VARIANTS && e == hipSuccess; ++v) {
+        if (v == 1) continue;
+        b->variant = v;
+        // trial steps read the current buffer and write the other one
+        e = b->step_once(b->stream, b->cur);
+        if (e == hipSuccess) e = hipEventRecord(t0, b->stream);
+        for (int r = 0; r < 3 && e == hipSuccess; ++r) e = b->step_once(b->stream, b->cur);
+        if (e == hipSuccess) e = hipEventRecord(t1, b->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(t1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+        if (e == hipSuccess && ms < best_ms) { best_ms = ms; best = v; }
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    b->variant = keep;
+    if (e != hipSuccess) return hip_fail(e, "batched tuning");
+    holb_batch_set_variant(b, best);
+    if (variant_out) *variant_out = best;
+    return HOLB_OK;
+}
+
+holb_status holb_batch_destroy(holb_batch* b)
+{
+    delete b;
+    return HOLB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,314 @@
+// C ABI of the library: configuration checks, workspace layout, state
+// bookkeeping and dispatch to the kernel launchers.  No device memory is
+// allocated here; the caller owns the workspace.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/holb.h"
+#include "holb_host.h"
+#include "holb_internal.h"
+
+using namespace holb;
+
+namespace holb {
+thread_local std::string g_last_error;
+}
+
+namespace {
+
+struct Layout {
+    size_t elem = 4;          // bytes per stored population
+    size_t pitch = 0;         // elements per population plane
+    size_t pop_bytes = 0;     // one population buffer
+    size_t pop_off[2] = {0, 0};
+    size_t aux_off = 0, aux_bytes = 0;
+    size_t tgt_off[2] = {0, 0};
+    size_t tgt_bytes = 0;
+    size_t part_off = 0;
+    int max_partials = 0;
+    size_t out_off = 0;
+    size_t err_off = 0;
+    size_t total = 0;
+};
+
+Layout layout_of(const holb_config* c)
+{
+    Layout L;
+    const int Q = lattice_Q(c->lattice), D = lattice_D(c->lattice);
+    const size_t N = (size_t)c->nx * c->ny * c->nz;
+    L.elem = c->storage == HOLB_STORE_F32 ? 4 : 2;
+    L.pitch = align_up(N, ALIGN / L.elem);
+    L.pop_bytes = (size_t)Q * L.pitch * L.elem;
+    size_t off = 0;
+    L.pop_off[0] = off; off = align_up(off + L.pop_bytes);
+    L.pop_off[1] = off; off = align_up(off + L.pop_bytes);
+    const int fam = family_of(c->sources);
+    L.aux_bytes = fam == FAM_PTENSOR ? N * 8 : (fam == FAM_THERMAL ? N * 4 : 0);
+    L.aux_off = off; off = align_up(off + L.aux_bytes);
+    if (c->walls) {
+        const size_t nlayer = D == 2 ? (size_t)c->nx : (size_t)c->nx * c->ny;
+        L.tgt_bytes = 6 * (size_t)(D + 2) * nlayer * sizeof(float);
+    }
+    L.tgt_off[0] = off; off = align_up(off + L.tgt_bytes);
+    L.tgt_off[1] = off; off = align_up(off + L.tgt_bytes);
+    L.max_partials = (int)((N + 255) / 256);
+    L.part_off = off; off = align_up(off + (size_t)L.max_partials * 5 * sizeof(double));
+    L.out_off = off; off = align_up(off + 8 * sizeof(double));
+    L.err_off = off; off = align_up(off + sizeof(unsigned));
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+struct holb_sim {
+    holb_config cfg;
+    Layout lay;
+    char* ws = nullptr;
+    hipStream_t stream = nullptr;
+    int cur = 0;            // buffer holding the current state
+    bool initialized = false;
+    int variant = 0;
+    LaunchCtx base;
+
+    LaunchCtx ctx(bool advance) const
+    {
+        LaunchCtx c = base;
+        const int nxt = 1 - cur;
+        c.pop_in = ws + lay.pop_off[cur];
+        c.pop_out = ws + lay.pop_off[nxt];
+        c.tgt_in = (const float*)(ws + lay.tgt_off[cur]);
+        c.tgt_out = (float*)(ws + lay.tgt_off[advance ? nxt : cur]);
+        c.variant = variant;
+        return c;
+    }
+};
+
+extern "C" {
+
+const char* holb_last_error(void) { return g_last_error.c_str(); }
+
+holb_status holb_lattice_info(int32_t lattice, int32_t* Q, int32_t* D, int32_t* c, double* w, double* c0sq)
+{
+    if (lattice != HOLB_D2Q37 && lattice != HOLB_D3Q39) return fail(HOLB_EINVAL, "unknown lattice %d", lattice);
+    if (Q) *Q = lattice_Q(lattice);
+    if (D) *D = lattice_D(lattice);
+    std::vector<int> cc(3 * 39);
+    lattice_table(lattice, cc.data(), w, c0sq);
+    if (c)
+        for (int k = 0; k < 3 * lattice_Q(lattice); ++k) c[k] = cc[k];
+    return HOLB_OK;
+}
+
+holb_status holb_workspace_size(const holb_config* cfg, size_t* bytes)
+{
+    holb_status s = validate(cfg);
+    if (s) return s;
+    if (!bytes) return fail(HOLB_EINVAL, "bytes is NULL");
+    *bytes = layout_of(cfg).total;
+    return HOLB_OK;
+}
+
+holb_status holb_create(const holb_config* cfg, void* dev_workspace, size_t bytes, void* hip_stream,
+                        holb_sim** out)
+{
+    if (!out) return fail(HOLB_EINVAL, "out is NULL");
+    *out = nullptr;
+    holb_status s = validate(cfg);
+    if (s) return s;
+    Layout L = layout_of(cfg);
+    if (!dev_workspace) return fail(HOLB_EINVAL, "workspace is NULL");
+    if ((uintptr_t)dev_workspace % ALIGN) return fail(HOLB_ESIZE, "workspace must be 256-byte aligned");
+    if (bytes < L.total) return fail(HOLB_ESIZE, "workspace has %zu bytes, needs %zu", bytes, L.total);
+    holb_sim* h = new (std::nothrow) holb_sim();
+    if (!h) return fail(HOLB_EINVAL, "out of host memory");
+    h->cfg = *cfg;
+    h->lay = L;
+    h->ws = (char*)dev_workspace;
+    h->stream = (hipStream_t)hip_stream;
+    LaunchCtx& c = h->base;
+    memset(&c, 0, sizeof c);
+    c.lattice = cfg->lattice;
+    c.storage = cfg->storage;
+    c.family = family_of(cfg->sources);
+    c.kp = params_of(cfg);
+    c.kp.err = (unsigned*)(h->ws + L.err_off);
+    c.kp.pitch = (long long)L.pitch;
+    c.aux_f = L.aux_bytes ? (float*)(h->ws + L.aux_off) : nullptr;
+    c.aux_d = L.aux_bytes ? (double*)(h->ws + L.aux_off) : nullptr;
+    c.partials = (double*)(h->ws + L.part_off);
+    c.max_partials = L.max_partials;
+    c.stream = h->stream;
+    *out = h;
+    return HOLB_OK;
+}
+
+static holb_status check_flags(holb_sim* s)
+{
+    unsigned flags = 0;
+    hipError_t e = hipMemcpyAsync(&flags, s->ws + s->lay.err_off, sizeof flags, hipMemcpyDeviceToHost, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "reading the error flags");
+    e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (flags) return fail(HOLB_ENUMERIC, "device numeric error flags 0x%x (1 density, 2 theta, 4 EOS)", flags);
+    return HOLB_OK;
+}
+
+holb_status holb_init(holb_sim* s, const float* rho, const float* u, const float* theta)
+{
+    if (!s) return fail(HOLB_EINVAL, "handle is NULL");
+    if (!rho || !u || (!theta && !s->cfg.isothermal)) return fail(HOLB_EINVAL, "field pointer is NULL");
+    if (((uintptr_t)rho | (uintptr_t)u | (uintptr_t)theta) % 4) return fail(HOLB_ESIZE, "fields must be 4-byte aligned");
+    hipError_t e = hipMemsetAsync(s->ws + s->lay.err_off, 0, sizeof(unsigned), s->stream);
+    if (e != hipSuccess) return hip_fail(e, "clearing the error flags");
+    // The init kernel writes the pre-streamed equilibrium into the current
+    // buffer and the initial fields as the wall targets of the first step.
+    LaunchCtx c = s->ctx(false);
+    c.pop_out = s->ws + s->lay.pop_off[s->cur];
+    c.tgt_out = (float*)(s->ws + s->lay.tgt_off[s->cur]);
+    e = launch_init(c, rho, u, theta ? theta : rho);
+    if (e != hipSuccess) return hip_fail(e, "init kernel");
+    s->initialized = true;
+    return HOLB_OK;
+}
+
+holb_status holb_step(holb_sim* s, int64_t n)
+{
+    if (!s) return fail(HOLB_EINVAL, "handle is NULL");
+    if (n < 0) return fail(HOLB_EINVAL, "n must be >= 0");
+    if (!s->initialized) return fail(HOLB_ESTATE, "holb_step before holb_init");
+    for (int64_t k = 0; k < n; ++k) {
+        hipError_t e = launch_step(s->ctx(true));
+        if (e != hipSuccess) return hip_fail(e, "step kernel");
+        s->cur = 1 - s->cur;
+    }
+    return HOLB_OK;
+}
+
+holb_status holb_fields(holb_sim* s, float* rho, float* u, float* theta)
+{
+    if (!s) return fail(HOLB_EINVAL, "handle is NULL");
+    if (!s->initialized) return fail(HOLB_ESTATE, "holb_fields before holb_init");
+    if (((uintptr_t)rho | (uintptr_t)u | (uintptr_t)theta) % 4) return fail(HOLB_ESIZE, "fields must be 4-byte aligned");
+    hipError_t e = launch_fields(s->ctx(false), rho, u, theta);
+    if (e != hipSuccess) return hip_fail(e, "fields kernel");
+    return check_flags(s);
+}
+
+holb_status holb_reduce(holb_sim* s, double out[5])
+{
+    if (!s || !out) return fail(HOLB_EINVAL, "NULL argument");
+    if (!s->initialized) return fail(HOLB_ESTATE, "holb_reduce before holb_init");
+    double* dout = (double*)(s->ws + s->lay.out_off);
+    hipError_t e = launch_reduce(s->ctx(false), dout);
+    if (e != hipSuccess) return hip_fail(e, "reduce kernel");
+    e = hipMemcpyAsync(out, dout, 5 * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "copying the totals");
+    return check_flags(s);
+}
+
+holb_status holb_error_flags(holb_sim* s, uint32_t* flags)
+{
+    if (!s || !flags) return fail(HOLB_EINVAL, "NULL argument");
+    unsigned f = 0;
+    hipError_t e = hipMemcpyAsync(&f, s->ws + s->lay.err_off, sizeof f, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(e, "reading the error flags");
+    *flags = f;
+    return HOLB_OK;
+}
+
+holb_status holb_state_bytes(holb_sim* s, size_t* bytes)
+{
+    if (!s || !bytes) return fail(HOLB_EINVAL, "NULL argument");
+    *bytes = s->lay.pop_bytes;
+    return HOLB_OK;
+}
+
+holb_status holb_get_state(holb_sim* s, void* dst, size_t bytes)
+{
+    if (!s || !dst) return fail(HOLB_EINVAL, "NULL argument");
+    if (bytes != s->lay.pop_bytes) return fail(HOLB_ESIZE, "state is %zu bytes, got %zu", s->lay.pop_bytes, bytes);
+    hipError_t e = hipMemcpyAsync(dst, s->ws + s->lay.pop_off[s->cur], bytes, hipMemcpyDeviceToDevice, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "copying the state out");
+    return HOLB_OK;
+}
+
+holb_status holb_set_state(holb_sim* s, const void* src, size_t bytes)
+{
+    if (!s || !src) return fail(HOLB_EINVAL, "NULL argument");
+    if (bytes != s->lay.pop_bytes) return fail(HOLB_ESIZE, "state is %zu bytes, got %zu", s->lay.pop_bytes, bytes);
+    if (s->cfg.walls && !s->initialized) return fail(HOLB_ESTATE, "walled domains need holb_init before holb_set_state");
+    hipError_t e = hipMemcpyAsync(s->ws + s->lay.pop_off[s->cur], src, bytes, hipMemcpyDeviceToDevice, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "copying the state in");
+    s->initialized = true;
+    return HOLB_OK;
+}
+
+holb_status holb_num_variants(holb_sim* s, int32_t* n)
+{
+    if (!s || !n) return fail(HOLB_EINVAL, "NULL argument");
+    *n = num_variants(s->base);
+    return HOLB_OK;
+}
+
+holb_status holb_set_variant(holb_sim* s, int32_t variant)
+{
+    if (!s) return fail(HOLB_EINVAL, "handle is NULL");
+    if (variant < 0 || variant >= num_variants(s->base) || !variant_supported(s->base, variant))
+        return fail(HOLB_EUNSUPPORTED, "variant %d does not apply to this configuration", variant);
+    s->variant = variant;
+    return HOLB_OK;
+}
+
+holb_status holb_tune(holb_sim* s, int32_t* variant_out)
+{
+    if (!s) return fail(HOLB_EINVAL, "handle is NULL");
+    if (!s->initialized) return fail(HOLB_ESTATE, "holb_tune before holb_init");
+    // Trial steps read the current buffer and write the other one (and the
+    // other wall-target buffer); the current state is left untouched.
+    hipEvent_t t0, t1;
+    hipError_t e = hipEventCreate(&t0);
+    if (e == hipSuccess) e = hipEventCreate(&t1);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    int best = s->variant;
+    float best_ms = 1e30f;
+    const int nv = num_variants(s->base);
+    for (int v = 0; v < nv && e == hipSuccess; ++v) {
+        if (!variant_supported(s->base, v)) continue;
+        LaunchCtx c = s->ctx(true);
+        c.variant = v;
+        e = launch_step(c);  // warm-up
+        if (e != hipSuccess) break;
+        const int reps = 3;
+        e = hipEventRecord(t0, s->stream);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_step(c);
+        if (e == hipSuccess) e = hipEventRecord(t1, s->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(t1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+        if (e == hipSuccess && ms < best_ms) { best_ms = ms; best = v; }
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    if (e != hipSuccess) return hip_fail(e, "tuning");
+    s->variant = best;
+    if (variant_out) *variant_out = best;
+    return HOLB_OK;
+}
+
+holb_status holb_destroy(holb_sim* s)
+{
+    delete s;
+    return HOLB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,275 @@
+// Per-cell device code shared by every kernel variant: pull streaming, wall
+// closure, shifted moments, stencil sources and the fused collision.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "holb_device.h"
+
+namespace holb {
+
+// Block index remapped so that the eight XCDs (which receive blocks
+// round-robin) each get a contiguous range of cells, keeping the pull
+// neighbourhood of a block in the same L2.
+__device__ __forceinline__ int xcd_block()
+{
+    const int nb = gridDim.x, b = blockIdx.x;
+    if (nb % 8) return b;
+    return (b % 8) * (nb / 8) + b / 8;
+}
+
+template <class L>
+__device__ __forceinline__ void cell_coords(const KParams& p, int cell, int& x, int& y, int& z)
+{
+    x = cell % p.nx;
+    int r = cell / p.nx;
+    y = r % p.ny;
+    z = r / p.ny;
+}
+
+// Pull the Q populations of node (x, y, z).  Along the wall-normal axis of a
+// walled domain, sources outside [0, n) are not read; their bits are returned.
+template <class L, int ST>
+__device__ __forceinline__ uint64_t pull_cell(const KParams& p, const typename Codec<ST>::T* __restrict__ fin,
+                                              int x, int y, int z, float (&f)[L::Q])
+{
+    using LL = Lat<L>;
+    const bool walls = p.walls;
+    int xs[7], ys[7], zs[7];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+        xs[k] = wrapc(x + k - 3, p.nx);
+        ys[k] = (L::D == 2 && walls) ? y + k - 3 : wrapc(y + k - 3, p.ny);
+        zs[k] = (L::D == 3) ? (walls ? z + k - 3 : wrapc(z + k - 3, p.nz)) : 0;
+    }
+    uint64_t unk = 0;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const int sx = xs[3 - L::cx[i]], sy = ys[3 - L::cy[i]], sz = zs[3 - L::cz[i]];
+        bool known = true;
+        if (walls) {
+            const int kw = (L::D == 2) ? sy : sz;
+            const int nw = (L::D == 2) ? p.ny : p.nz;
+            known = (kw >= 0 && kw < nw);
+        }
+        if (known) {
+            const int idx = (sz * p.ny + sy) * p.nx + sx;
+            f[i] = Codec<ST>::dec(fin[(long long)i * p.pitch + idx], LL::w(i), p.ref[i]);
+        } else {
+            f[i] = 0.0f;
+            unk |= 1ull << i;
+        }
+    }
+    return unk;
+}
+
+template <class L>
+__device__ __forceinline__ void wall_coord(const KParams& p, int x, int y, int z, int& kw, int& nw, int& cil)
+{
+    if (L::D == 2) { kw = y; nw = p.ny; cil = x; }
+    else { kw = z; nw = p.nz; cil = x + p.nx * y; }
+}
+
+// Pull + wall closure + shifted moments (no stencil force).  Shared by every
+// pass over the state so that they agree bitwise.
+template <class L, int ST>
+__device__ __forceinline__ void load_state(const KParams& p, const typename Codec<ST>::T* __restrict__ fin,
+                                           const float* __restrict__ tgt_in, int x, int y, int z,
+                                           float (&f)[L::Q], float& rho, float (&j)[3], float& e)
+{
+    uint64_t unk = pull_cell<L, ST>(p, fin, x, y, z, f);
+    if (p.walls && unk) {
+        int kw, nw, cil;
+        wall_coord<L>(p, x, y, z, kw, nw, cil);
+        const int slot = wall_slot(kw, nw);
+        float t[5];
+#pragma unroll
+        for (int c = 0; c < L::D + 2; ++c) t[c] = tgt_in[((long long)slot * (L::D + 2) + c) * p.nlayer + cil];
+        const int wall = kw == 0 ? 0 : (kw == nw - 1 ? 1 : -1);
+        tms_fill<L>(p, f, unk, wall, t);
+    }
+    moments<L>(f, rho, j, e);
+}
+
+// Eq. (3.8): F^SC(x) = -G psi(x) sum_i w_i psi(x + c_i) c_i, FP64, periodic.
+template <class L>
+__device__ __forceinline__ void sc_force(const KParams& p, const double* __restrict__ psi, int x, int y, int z,
+                                         double& psi_x, double (&F)[3])
+{
+    double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) {
+        const int sx = wrapc(x + L::cx[i], p.nx), sy = wrapc(y + L::cy[i], p.ny);
+        const int sz = L::D == 3 ? wrapc(z + L::cz[i], p.nz) : 0;
+        const double ps = psi[(sz * p.ny + sy) * p.nx + sx] * L::shell_w[L::shell[i]];
+        if (L::cx[i]) acc[0] = fma((double)L::cx[i], ps, acc[0]);
+        if (L::cy[i]) acc[1] = fma((double)L::cy[i], ps, acc[1]);
+        if (L::cz[i]) acc[2] = fma((double)L::cz[i], ps, acc[2]);
+    }
+    psi_x = psi[(z * p.ny + y) * p.nx + x];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) F[a] = -p.G * psi_x * acc[a];
+}
+
+// Pressure-tensor coefficient of Eq. (3.12) from F^SC and psi (FP64).
+__device__ __forceinline__ float ptensor_coef(const KParams& p, double psi_x, const double (&F)[3])
+{
+    const double F2 = F[0] * F[0] + F[1] * F[1] + F[2] * F[2];
+    return (float)(p.pfac * F2 / (psi_x * psi_x));
+}
+
+// Section 3.2: grad theta by central differences; one-sided first differences
+// on the wall layers of a walled domain.
+template <class L>
+__device__ __forceinline__ void grad_theta(const KParams& p, const float* __restrict__ th, int x, int y, int z,
+                                           float (&g)[3])
+{
+    auto at = [&](int xx, int yy, int zz) { return th[(zz * p.ny + yy) * p.nx + xx]; };
+    g[0] = 0.5f * (at(wrapc(x + 1, p.nx), y, z) - at(wrapc(x - 1, p.nx), y, z));
+    g[2] = 0.0f;
+    if (L::D == 2) {
+        if (p.walls) {
+            if (y == 0) g[1] = at(x, 1, z) - at(x, 0, z);
+            else if (y == p.ny - 1) g[1] = at(x, y, z) - at(x, y - 1, z);
+            else g[1] = 0.5f * (at(x, y + 1, z) - at(x, y - 1, z));
+        } else {
+            g[1] = 0.5f * (at(x, wrapc(y + 1, p.ny), z) - at(x, wrapc(y - 1, p.ny), z));
+        }
+    } else {
+        g[1] = 0.5f * (at(x, wrapc(y + 1, p.ny), z) - at(x, wrapc(y - 1, p.ny), z));
+        if (p.walls) {
+            if (z == 0) g[2] = at(x, y, 1) - at(x, y, 0);
+            else if (z == p.nz - 1) g[2] = at(x, y, z) - at(x, y, z - 1);
+            else g[2] = 0.5f * (at(x, y, z + 1) - at(x, y, z - 1));
+        } else {
+            g[2] = 0.5f * (at(x, y, wrapc(z + 1, p.nz)) - at(x, y, wrapc(z - 1, p.nz)));
+        }
+    }
+}
+
+template <class L>
+__device__ __forceinline__ void write_targets(const KParams& p, float* __restrict__ tgt_out, int x, int y, int z,
+                                              const Macro& m)
+{
+    int kw, nw, cil;
+    wall_coord<L>(p, x, y, z, kw, nw, cil);
+    const int slot = wall_slot(kw, nw);
+    if (slot < 0) return;
+    float* t = tgt_out + (long long)slot * (L::D + 2) * p.nlayer + cil;
+    t[0] = m.rho;
+#pragma unroll
+    for (int a = 0; a < L::D; ++a) t[(long long)(1 + a) * p.nlayer] = m.u[a];
+    t[(long long)(1 + L::D) * p.nlayer] = m.theta;
+}
+
+template <class L, int ST, int FAM>
+__device__ __forceinline__ void full_macro(const KParams& p, const float* __restrict__ aux_f,
+                                           const double* __restrict__ aux_d, int x, int y, int z, float rho,
+                                           const float (&j)[3], float e, Macro& m, float& pc)
+{
+    float Fext[3] = {0.f, 0.f, 0.f};
+    pc = 0.0f;
+    if (FAM == FAM_PTENSOR) {
+        double psi_x, Fsc[3];
+        sc_force<L>(p, aux_d, x, y, z, psi_x, Fsc);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) Fext[a] = (float)Fsc[a];
+        pc = ptensor_coef(p, psi_x, Fsc);
+    }
+    macro_from_moments<L>(p, rho, j, e, Fext, m);
+}
+
+// One full step of one cell: pull, closure, moments, sources, collision and
+// store of the post-collision populations at `cell` of fout.
+template <class L, int ST, int FAM>
+__device__ __forceinline__ void step_cell(const KParams& p, const typename Codec<ST>::T* __restrict__ fin,
+                                          typename Codec<ST>::T* __restrict__ fout, const float* __restrict__ aux_f,
+                                          const double* __restrict__ aux_d, const float* __restrict__ tgt_in,
+                                          float* __restrict__ tgt_out, int cell)
+{
+    using LL = Lat<L>;
+    int x, y, z;
+    cell_coords<L>(p, cell, x, y, z);
+    float f[L::Q], rho, j[3], e;
+    load_state<L, ST>(p, fin, tgt_in, x, y, z, f, rho, j, e);
+    Macro m;
+    float pc;
+    full_macro<L, ST, FAM>(p, aux_f, aux_d, x, y, z, rho, j, e, m, pc);
+    if (p.walls) write_targets<L>(p, tgt_out, x, y, z, m);
+    float gT[3] = {0.f, 0.f, 0.f};
+    float hc = 0.0f;
+    if (FAM == FAM_THERMAL) {
+        grad_theta<L>(p, aux_f, x, y, z, gT);
+        hc = p.hfac * m.rho * m.theta;
+    }
+    collide<L>(p, f, m, hc, gT, pc);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i)
+        fout[(long long)i * p.pitch + cell] = Codec<ST>::enc(f[i], LL::invw(i), p.ref[i]);
+}
+
+// Field pass of one cell: theta (thermal family) or psi (pressure-tensor
+// family) of the current state, read by the stencil of the following pass.
+template <class L, int ST, int FAM>
+__device__ __forceinline__ void aux_cell(const KParams& p, const typename Codec<ST>::T* __restrict__ fin,
+                                         const float* __restrict__ tgt_in, float* __restrict__ aux_f,
+                                         double* __restrict__ aux_d, int cell)
+{
+    int x, y, z;
+    cell_coords<L>(p, cell, x, y, z);
+    float f[L::Q], rho, j[3], e;
+    load_state<L, ST>(p, fin, tgt_in, x, y, z, f, rho, j, e);
+    if (FAM == FAM_PTENSOR) {
+        bool bad = false;
+        aux_d[cell] = psi_vdw(p, (double)rho, L::c0sq, bad);
+        if (bad) raise_err(p, HOLB_ERR_EOS_BIT);
+    } else {
+        const float z3[3] = {0.f, 0.f, 0.f};
+        Macro m;
+        macro_from_moments<L>(p, rho, j, e, z3, m);
+        aux_f[cell] = m.theta;
+    }
+}
+
+// Initial state of one cell: f^0_i(x) = f^eq_i(rho, u, theta)(x), written to
+// the slot x - c_i that the first pull of node x reads.
+template <class L, int ST>
+__device__ __forceinline__ void init_cell(const KParams& p, const float* __restrict__ rho,
+                                          const float* __restrict__ u, const float* __restrict__ theta,
+                                          typename Codec<ST>::T* __restrict__ fout, float* __restrict__ tgt, int cell)
+{
+    using LL = Lat<L>;
+    int x, y, z;
+    cell_coords<L>(p, cell, x, y, z);
+    Macro m;
+    m.rho = rho[cell];
+    m.u[0] = m.u[1] = m.u[2] = 0.f;
+#pragma unroll
+    for (int a = 0; a < L::D; ++a) m.u[a] = u[(long long)a * p.N + cell];
+    m.theta = (p.flags & KF_ISO) ? 1.0f : theta[cell];
+    if (!(m.rho > 0.0f) || !(m.rho < 3.0e38f)) raise_err(p, HOLB_ERR_DENSITY_BIT);
+    if (!(m.theta > 0.0f) || !(m.theta < 3.0e38f)) raise_err(p, HOLB_ERR_THETA_BIT);
+    if (p.walls) write_targets<L>(p, tgt, x, y, z, m);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        int dx = wrapc(x - L::cx[i], p.nx);
+        int dy, dz;
+        bool inside = true;
+        if (L::D == 2) {
+            dz = 0;
+            dy = y - L::cy[i];
+            if (p.walls) inside = dy >= 0 && dy < p.ny;
+            else dy = wrapc(dy, p.ny);
+        } else {
+            dy = wrapc(y - L::cy[i], p.ny);
+            dz = z - L::cz[i];
+            if (p.walls) inside = dz >= 0 && dz < p.nz;
+            else dz = wrapc(dz, p.nz);
+        }
+        if (!inside) continue;
+        const float fe = feq_one<L>(i, m.rho, m.u, m.theta);
+        fout[(long long)i * p.pitch + (dz * p.ny + dy) * p.nx + dx] = Codec<ST>::enc(fe, LL::invw(i), p.ref[i]);
+    }
+}
+
+}  // namespace holb

@@ -1,0 +1,48 @@
+// Host-side interface between the C ABI (holb_capi.hip) and the kernel
+// launchers (holb_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "holb_params.h"
+
+namespace holb {
+
+// One launch's worth of device pointers and parameters.
+struct LaunchCtx {
+    int lattice;          // 0 D2Q37, 1 D3Q39
+    int storage;          // Storage
+    int family;           // Family
+    int variant;          // kernel variant (0 = generic)
+    KParams kp;
+    const void* pop_in;   // current state (post-collision of the last step)
+    void* pop_out;        // next state
+    float* aux_f;         // theta field (thermal split path)
+    double* aux_d;        // psi field (pressure-tensor path)
+    const float* tgt_in;  // wall targets read this step
+    float* tgt_out;       // wall targets written this step
+    double* partials;     // reduction partials
+    int max_partials;     // capacity in blocks
+    hipStream_t stream;
+};
+
+int num_variants(const LaunchCtx& c);
+bool variant_supported(const LaunchCtx& c, int variant);
+
+hipError_t launch_init(const LaunchCtx& c, const float* rho, const float* u, const float* theta);
+hipError_t launch_step(const LaunchCtx& c);
+hipError_t launch_aux(const LaunchCtx& c);  // psi / theta field of the current state
+hipError_t launch_fields(const LaunchCtx& c, float* rho, float* u, float* theta);
+hipError_t launch_reduce(const LaunchCtx& c, double* out_dev);
+int reduce_blocks(const LaunchCtx& c);
+
+// Reference f^eq_i(rho, u, theta) / w_i of the 16-bit deviation storage, in
+// the library's velocity order (host, FP64 arithmetic of Eq. 2.2).
+void deviation_reference(int lattice, double rho, const double* u, double theta, float* ref_out);
+
+// Velocity set in library order.
+int lattice_Q(int lattice);
+int lattice_D(int lattice);
+void lattice_table(int lattice, int* c, double* w, double* c0sq);
+
+}  // namespace holb

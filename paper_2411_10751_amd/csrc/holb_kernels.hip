@@ -1,0 +1,324 @@
+// gfx950 kernels of the high-order lattice Boltzmann step and their launchers.
+//
+// Data layout: populations are structure-of-arrays, Q planes of `pitch`
+// elements (256-byte aligned), cell = x + nx * (y + ny * z).  The state buffer
+// holds the post-collision populations of the last step; a step pulls
+// f^_i(x) = buf[i][x - c_i] (streaming, left side of Eq. 4.4), applies the wall
+// closure, forms the shifted moments (Eq. 4.5), the sources and the collision,
+// and writes the post-collision populations of x into the other buffer.
+//
+// Generic variant: one cell per thread, 256-thread blocks along x.  Stencil
+// sources (temperature gradient, pseudopotential force) read a field written
+// by a preceding pass over the same state (launch_aux).
+#include <hip/hip_runtime.h>
+
+#include "holb_cell.h"
+#include "holb_device.h"
+#include "holb_internal.h"
+#include "holb_march.h"
+
+namespace holb {
+
+constexpr int GEN_BLOCK = 256;
+
+// --------------------------------------------------------------- kernels
+
+template <class L, int ST>
+__global__ void __launch_bounds__(GEN_BLOCK)
+k_init(const KParams p, const float* __restrict__ rho, const float* __restrict__ u,
+       const float* __restrict__ theta, typename Codec<ST>::T* __restrict__ fout, float* __restrict__ tgt)
+{
+    const int cell = xcd_block() * GEN_BLOCK + threadIdx.x;
+    if (cell < p.N) init_cell<L, ST>(p, rho, u, theta, fout, tgt, cell);
+}
+
+template <class L, int ST, int FAM>
+__global__ void __launch_bounds__(GEN_BLOCK)
+k_aux(const KParams p, const typename Codec<ST>::T* __restrict__ fin, const float* __restrict__ tgt_in,
+      float* __restrict__ aux_f, double* __restrict__ aux_d)
+{
+    const int cell = xcd_block() * GEN_BLOCK + threadIdx.x;
+    if (cell < p.N) aux_cell<L, ST, FAM>(p, fin, tgt_in, aux_f, aux_d, cell);
+}
+
+template <class L, int ST, int FAM>
+__global__ void __launch_bounds__(GEN_BLOCK)
+k_step(const KParams p, const typename Codec<ST>::T* __restrict__ fin, typename Codec<ST>::T* __restrict__ fout,
+       const float* __restrict__ aux_f, const double* __restrict__ aux_d, const float* __restrict__ tgt_in,
+       float* __restrict__ tgt_out)
+{
+    const int cell = xcd_block() * GEN_BLOCK + threadIdx.x;
+    if (cell < p.N) step_cell<L, ST, FAM>(p, fin, fout, aux_f, aux_d, tgt_in, tgt_out, cell);
+}
+
+template <class L, int ST, int FAM>
+__global__ void __launch_bounds__(GEN_BLOCK)
+k_fields(const KParams p, const typename Codec<ST>::T* __restrict__ fin, const float* __restrict__ aux_f,
+         const double* __restrict__ aux_d, const float* __restrict__ tgt_in, float* __restrict__ rho_out,
+         float* __restrict__ u_out, float* __restrict__ th_out)
+{
+    const int cell = xcd_block() * GEN_BLOCK + threadIdx.x;
+    if (cell >= p.N) return;
+    int x, y, z;
+    cell_coords<L>(p, cell, x, y, z);
+    float f[L::Q], rho, j[3], e;
+    load_state<L, ST>(p, fin, tgt_in, x, y, z, f, rho, j, e);
+    Macro m;
+    float pc;
+    full_macro<L, ST, FAM>(p, aux_f, aux_d, x, y, z, rho, j, e, m, pc);
+    if (rho_out) rho_out[cell] = m.rho;
+    if (u_out) {
+#pragma unroll
+        for (int a = 0; a < L::D; ++a) u_out[(long long)a * p.N + cell] = m.u[a];
+    }
+    if (th_out) th_out[cell] = m.theta;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Block partials of mass, momentum and energy in FP64 (wavefront shuffles,
+// then LDS across the block's waves).
+template <class L, int ST, int FAM>
+__global__ void __launch_bounds__(GEN_BLOCK)
+k_reduce(const KParams p, const typename Codec<ST>::T* __restrict__ fin, const float* __restrict__ aux_f,
+         const double* __restrict__ aux_d, const float* __restrict__ tgt_in, double* __restrict__ partials)
+{
+    __shared__ double red[GEN_BLOCK / 64][5];
+    const int cell = blockIdx.x * GEN_BLOCK + threadIdx.x;
+    double v[5] = {0, 0, 0, 0, 0};
+    if (cell < p.N) {
+        int x, y, z;
+        cell_coords<L>(p, cell, x, y, z);
+        float f[L::Q], rho, j[3], e;
+        load_state<L, ST>(p, fin, tgt_in, x, y, z, f, rho, j, e);
+        Macro m;
+        float pc;
+        full_macro<L, ST, FAM>(p, aux_f, aux_d, x, y, z, rho, j, e, m, pc);
+        const double r = m.rho;
+        v[0] = r;
+        v[1] = r * (double)m.u[0];
+        v[2] = r * (double)m.u[1];
+        v[3] = r * (double)m.u[2];
+        const double uu = (double)m.u[0] * m.u[0] + (double)m.u[1] * m.u[1] + (double)m.u[2] * m.u[2];
+        v[4] = 0.5 * (r * uu + r * (L::D * L::c0sq) * (double)m.theta);
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        double s = wave_sum(v[k]);
+        if (lane == 0) red[wv][k] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        double s = 0.0;
+        for (int w = 0; w < GEN_BLOCK / 64; ++w) s += red[w][threadIdx.x];
+        partials[(long long)blockIdx.x * 5 + threadIdx.x] = s;
+    }
+}
+
+// Deterministic second pass: fixed strided order, then a fixed tree.
+__global__ void __launch_bounds__(256) k_reduce_final(const double* __restrict__ partials, int nblocks,
+                                                      double* __restrict__ out)
+{
+    __shared__ double red[4][5];
+    double v[5] = {0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nblocks; b += 256)
+#pragma unroll
+        for (int k = 0; k < 5; ++k) v[k] += partials[(long long)b * 5 + k];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        double s = wave_sum(v[k]);
+        if (lane == 0) red[wv][k] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) out[threadIdx.x] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) +
+                                           red[3][threadIdx.x];
+}
+
+// -------------------------------------------------------------- launchers
+
+static inline int nblocks_for(int N) { return (N + GEN_BLOCK - 1) / GEN_BLOCK; }
+
+template <class L, int ST, int FAM>
+struct Launch {
+    using T = typename Codec<ST>::T;
+
+    static hipError_t init(const LaunchCtx& c, const float* rho, const float* u, const float* th)
+    {
+        hipLaunchKernelGGL((k_init<L, ST>), dim3(nblocks_for(c.kp.N)), dim3(GEN_BLOCK), 0, c.stream, c.kp, rho, u,
+                           th, (T*)c.pop_out, (float*)c.tgt_out);
+        return hipGetLastError();
+    }
+
+    static hipError_t aux(const LaunchCtx& c)
+    {
+        if (FAM == FAM_LOCAL) return hipSuccess;
+        hipLaunchKernelGGL((k_aux<L, ST, FAM>), dim3(nblocks_for(c.kp.N)), dim3(GEN_BLOCK), 0, c.stream, c.kp,
+                           (const T*)c.pop_in, c.tgt_in, c.aux_f, c.aux_d);
+        return hipGetLastError();
+    }
+
+    static hipError_t step(const LaunchCtx& c)
+    {
+        if (c.variant != 0) {
+            hipError_t r = march_step<L, ST, FAM>(c);
+            if (r != hipErrorNotSupported) return r;
+        }
+        hipError_t r = aux(c);
+        if (r != hipSuccess) return r;
+        hipLaunchKernelGGL((k_step<L, ST, FAM>), dim3(nblocks_for(c.kp.N)), dim3(GEN_BLOCK), 0, c.stream, c.kp,
+                           (const T*)c.pop_in, (T*)c.pop_out, c.aux_f, c.aux_d, c.tgt_in, c.tgt_out);
+        return hipGetLastError();
+    }
+
+    static hipError_t fields(const LaunchCtx& c, float* rho, float* u, float* th)
+    {
+        if (FAM == FAM_PTENSOR) {
+            hipError_t r = aux(c);
+            if (r != hipSuccess) return r;
+        }
+        hipLaunchKernelGGL((k_fields<L, ST, FAM>), dim3(nblocks_for(c.kp.N)), dim3(GEN_BLOCK), 0, c.stream, c.kp,
+                           (const T*)c.pop_in, c.aux_f, c.aux_d, c.tgt_in, rho, u, th);
+        return hipGetLastError();
+    }
+
+    static hipError_t reduce(const LaunchCtx& c, double* out)
+    {
+        if (FAM == FAM_PTENSOR) {
+            hipError_t r = aux(c);
+            if (r != hipSuccess) return r;
+        }
+        const int nb = nblocks_for(c.kp.N);
+        if (nb > c.max_partials) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_reduce<L, ST, FAM>), dim3(nb), dim3(GEN_BLOCK), 0, c.stream, c.kp,
+                           (const T*)c.pop_in, c.aux_f, c.aux_d, c.tgt_in, c.partials);
+        hipError_t r = hipGetLastError();
+        if (r != hipSuccess) return r;
+        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, c.stream, c.partials, nb, out);
+        return hipGetLastError();
+    }
+};
+
+template <class L, int ST>
+static hipError_t dispatch_family(const LaunchCtx& c, int op, const float* a, const float* b, const float* d,
+                                  float* o1, float* o2, float* o3, double* dout)
+{
+#define HOLB_OPS(FAM)                                              \
+    switch (op) {                                                  \
+    case 0: return Launch<L, ST, FAM>::init(c, a, b, d);           \
+    case 1: return Launch<L, ST, FAM>::step(c);                    \
+    case 2: return Launch<L, ST, FAM>::aux(c);                     \
+    case 3: return Launch<L, ST, FAM>::fields(c, o1, o2, o3);      \
+    case 4: return Launch<L, ST, FAM>::reduce(c, dout);            \
+    }
+    switch (c.family) {
+    case FAM_LOCAL: HOLB_OPS(FAM_LOCAL) break;
+    case FAM_THERMAL: HOLB_OPS(FAM_THERMAL) break;
+    case FAM_PTENSOR: HOLB_OPS(FAM_PTENSOR) break;
+    }
+#undef HOLB_OPS
+    return hipErrorInvalidValue;
+}
+
+template <class L>
+static hipError_t dispatch_storage(const LaunchCtx& c, int op, const float* a, const float* b, const float* d,
+                                   float* o1, float* o2, float* o3, double* dout)
+{
+    switch (c.storage) {
+    case ST_F32: return dispatch_family<L, ST_F32>(c, op, a, b, d, o1, o2, o3, dout);
+    case ST_F16: return dispatch_family<L, ST_F16>(c, op, a, b, d, o1, o2, o3, dout);
+    case ST_BF16: return dispatch_family<L, ST_BF16>(c, op, a, b, d, o1, o2, o3, dout);
+    }
+    return hipErrorInvalidValue;
+}
+
+static hipError_t dispatch(const LaunchCtx& c, int op, const float* a = nullptr, const float* b = nullptr,
+                           const float* d = nullptr, float* o1 = nullptr, float* o2 = nullptr,
+                           float* o3 = nullptr, double* dout = nullptr)
+{
+    if (c.lattice == 0) return dispatch_storage<D2Q37>(c, op, a, b, d, o1, o2, o3, dout);
+    if (c.lattice == 1) return dispatch_storage<D3Q39>(c, op, a, b, d, o1, o2, o3, dout);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_init(const LaunchCtx& c, const float* rho, const float* u, const float* theta)
+{
+    return dispatch(c, 0, rho, u, theta);
+}
+hipError_t launch_step(const LaunchCtx& c) { return dispatch(c, 1); }
+hipError_t launch_aux(const LaunchCtx& c) { return dispatch(c, 2); }
+hipError_t launch_fields(const LaunchCtx& c, float* rho, float* u, float* theta)
+{
+    return dispatch(c, 3, nullptr, nullptr, nullptr, rho, u, theta);
+}
+hipError_t launch_reduce(const LaunchCtx& c, double* out_dev)
+{
+    return dispatch(c, 4, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, out_dev);
+}
+int reduce_blocks(const LaunchCtx& c) { return nblocks_for(c.kp.N); }
+
+int num_variants(const LaunchCtx& c) { return 1 + march_num_variants(c); }
+
+bool variant_supported(const LaunchCtx& c, int variant)
+{
+    if (variant == 0) return true;
+    return march_variant_supported(c, variant);
+}
+
+// ------------------------------------------------------- host-side tables
+
+template <class L>
+static void table_of(int* c, double* w, double* c0sq)
+{
+    for (int i = 0; i < L::Q; ++i) {
+        if (c) {
+            c[3 * i + 0] = L::cx[i];
+            c[3 * i + 1] = L::cy[i];
+            c[3 * i + 2] = L::cz[i];
+        }
+        if (w) w[i] = L::shell_w[L::shell[i]];
+    }
+    if (c0sq) *c0sq = L::c0sq;
+}
+
+int lattice_Q(int lattice) { return lattice == 0 ? D2Q37::Q : D3Q39::Q; }
+int lattice_D(int lattice) { return lattice == 0 ? D2Q37::D : D3Q39::D; }
+void lattice_table(int lattice, int* c, double* w, double* c0sq)
+{
+    if (lattice == 0) table_of<D2Q37>(c, w, c0sq);
+    else table_of<D3Q39>(c, w, c0sq);
+}
+
+// Eq. (2.2) in FP64 on the host, divided by w_i: the reference state of the
+// 16-bit deviation storage.
+template <class L>
+static void dev_ref(double rho, const double* u, double theta, float* out)
+{
+    const double ic = 1.0 / L::c0sq, D = L::D;
+    const double uu = (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) * ic;
+    const double thb = theta - 1.0;
+    for (int i = 0; i < L::Q; ++i) {
+        const double a = (L::cx[i] * u[0] + L::cy[i] * u[1] + L::cz[i] * u[2]) * ic;
+        const double xx = (L::cx[i] * L::cx[i] + L::cy[i] * L::cy[i] + L::cz[i] * L::cz[i]) * ic;
+        const double t = 1.0 + a + 0.5 * a * a - 0.5 * uu + 0.5 * thb * (xx - D) + a * a * a / 6.0 -
+                         0.5 * a * uu + 0.5 * a * thb * (xx - (D + 2)) + a * a * a * a / 24.0 -
+                         0.25 * a * a * uu + 0.125 * uu * uu +
+                         0.25 * thb * (a * a * (xx - (D + 4)) + uu * ((D + 2) - xx)) +
+                         0.125 * thb * thb * (xx * xx - 2.0 * (D + 2) * xx + D * (D + 2));
+        out[i] = (float)(rho * t);
+    }
+}
+
+void deviation_reference(int lattice, double rho, const double* u, double theta, float* ref_out)
+{
+    if (lattice == 0) dev_ref<D2Q37>(rho, u, theta, ref_out);
+    else dev_ref<D3Q39>(rho, u, theta, ref_out);
+}
+
+}  // namespace holb

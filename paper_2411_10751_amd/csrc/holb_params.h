@@ -1,0 +1,45 @@
+// Plain-old-data kernel parameters shared by the host runtime and the kernels.
+#pragma once
+
+#include <stdint.h>
+
+namespace holb {
+
+enum Storage { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2 };
+
+// Source families select the kernel template (register footprint differs);
+// the body force and the isothermal mode are runtime flags.
+enum Family { FAM_LOCAL = 0, FAM_THERMAL = 1, FAM_PTENSOR = 2 };
+
+enum : unsigned { KF_BODY = 1u, KF_ISO = 2u };
+
+enum : unsigned { HOLB_ERR_DENSITY_BIT = 1u, HOLB_ERR_THETA_BIT = 2u, HOLB_ERR_EOS_BIT = 4u };
+
+constexpr int QMAX = 39;
+
+struct KParams {
+    int nx, ny, nz;      // grid
+    int walls;           // 1: TMS walls normal to the last axis
+    int N;               // cells
+    int nlayer;          // cells per wall-normal layer (nx for 2D, nx*ny for 3D)
+    long long pitch;     // elements per population plane
+    unsigned flags;      // KF_*
+    float omega, kappa;  // 1/tau_hat and 1 - 1/(2 tau_hat)
+    float g[3];          // body-force acceleration
+    float hfac;          // (1 - 1/Pr) / 2
+    float twall[2];
+    float uwall[2][3];
+    double pfac;         // -(k / (2 D tau)) / (c0^2 G), tau = tau_hat - 1/2
+    double eos_a, eos_b, eos_T, G;
+    float ref[QMAX];     // f^eq_i(reference) / w_i for the 16-bit storage
+    unsigned* err;       // device error word
+};
+
+// Wall targets: 6 layers (3 per wall) x nlayer cells x (D + 2) floats, laid
+// out [layer slot][component][cell in layer].
+__host__ __device__ inline int wall_slot(int k, int n)
+{
+    return k < 3 ? k : (k >= n - 3 ? k - (n - 6) : -1);
+}
+
+}  // namespace holb

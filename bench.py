@@ -1,0 +1,200 @@
+"""Throughput of the fused high-order LBM step on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--storage f32|f16|bf16]
+
+Default workload: the D3Q39 Rayleigh-Benard box, 256^3 cells, body force +
+thermal-dissipation source, TMS walls normal to z, FP32 population storage.
+One step is one pass of the whole per-step update over every cell (wall
+closure, streaming, shifted moments, sources, equilibrium, collision, store);
+the timed region also ends with one FP64 conservation reduction.  Inputs are
+synthetic (seeded fields of the workload recipe) and resident in HBM before
+timing starts.
+
+Prints one JSON line with the throughput (MLUPS = cell updates / s / 1e6),
+the roofline of the step against MI355X HBM bandwidth, and the FP64 CPU oracle
+timed on a bounded sample of the same workload as a baseline.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS + % of HBM peak for fused collide-stream-source, FP32/FP16-store vs FP64"
+HBM_PEAK_GBS = 8000.0
+STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
+STORE_BYTES = {0: 4, 1: 2, 2: 2}
+DTYPE_NAME = {0: "f32", 1: "f32 (f16-deviation storage)", 2: "f32 (bf16-deviation storage)"}
+
+
+def workload(name):
+    from paper_2411_10751_amd import inputs
+    if name == "rb3d":
+        return inputs.rayleigh_benard_3d(n=256, steps=200)
+    if name == "thermal2d":
+        return inputs.thermal_2d(n=1024, steps=200)
+    if name == "ptensor2d":
+        return inputs.ptensor_2d(n=2048, steps=200)
+    if name == "body2d":
+        return inputs.body_force_2d(n=2048, steps=200)
+    raise SystemExit("unknown workload %s" % name)
+
+
+def cpu_baseline(name, storage):
+    """FP64 oracle on a bounded sample of the workload (about 10-30 s of CPU)."""
+    import numpy as np
+    from oracle import orc
+    from paper_2411_10751_amd import inputs
+    if name == "rb3d":
+        w = inputs.rayleigh_benard_3d(n=64, steps=20)
+        sample = "D3Q39 Rayleigh-Benard 64^3 with walls, body+thermal, 20 steps"
+    elif name == "thermal2d":
+        w = inputs.thermal_2d(n=256, steps=40)
+        sample = "D2Q37 thermal 256^2, 40 steps"
+    elif name == "ptensor2d":
+        w = inputs.ptensor_2d(n=256, steps=40, ndrops=6, rmin=10, rmax=20, gap=8)
+        sample = "D2Q37 pressure tensor 256^2 droplets, 40 steps"
+    else:
+        w = inputs.body_force_2d(n=256, steps=40)
+        sample = "D2Q37 body force 256^2, 40 steps"
+    c = w["config"]
+    s = orc.Sim(c["lattice"], c["nx"], c["ny"], c.get("nz", 1), tau_hat=c["tau_hat"], sources=c["sources"],
+                isothermal=c.get("isothermal", 0), g=c["g"], prandtl=c["prandtl"], eos_a=c["eos_a"],
+                eos_b=c["eos_b"], eos_T=c["eos_T"], sc_G=c["sc_G"], ptensor_k=c["ptensor_k"],
+                walls=c["walls"], theta_wall=c["theta_wall"], u_wall=c["u_wall"])
+    s.init(w["rho"].astype(np.float64), w["u"].astype(np.float64), w["theta"].astype(np.float64))
+    s.step(1)
+    t0 = time.perf_counter()
+    s.step(w["steps"])
+    dt = time.perf_counter() - t0
+    cells = c["nx"] * c["ny"] * c.get("nz", 1)
+    return {"value": round(cells * w["steps"] / dt / 1e6, 4), "unit": "MLUPS", "cores": orc.num_threads(),
+            "kind": "oracle", "sample": sample + " (FP64, %.1f s)" % dt}
+
+
+def traffic_from_profile(kernel, name, storage):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the kernel source as it is now."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.txt" % (name, {0: "f32", 1: "f16", 2: "bf16"}[storage]))
+    if not os.path.exists(path):
+        return None
+    src = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2411_10751_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            src.update(open(os.path.join(csrc, f), "rb").read())
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_sha256") != src.hexdigest() or vals.get("kernel") != kernel:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="rb3d", choices=["rb3d", "thermal2d", "ptensor2d", "body2d"])
+    ap.add_argument("--storage", default="f32", choices=list(STORAGE))
+    ap.add_argument("--variant", type=int, default=-1, help="-1: autotune")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the library has no multi-GPU path (each run fits one "
+              "MI355X); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2411_10751_amd import holb
+
+    storage = STORAGE[args.storage]
+    w = workload(args.workload)
+    cfg = dict(w["config"], storage=storage)
+    Q = 37 if cfg["lattice"] == 0 else 39
+    cells = cfg["nx"] * cfg["ny"] * cfg.get("nz", 1)
+    torch.cuda.set_device(0)
+    sim = holb.Sim(cfg)
+    sim.init(w["rho"], w["u"], w["theta"])
+    if args.variant >= 0:
+        sim.set_variant(args.variant)
+        variant = args.variant
+    else:
+        variant = sim.tune()
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    sim.step(args.steps)
+    e1.record(stream)
+    totals = sim.reduce()  # FP64 conservation totals (synchronises)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = e0.elapsed_time(e1) / args.steps
+
+    mlups = cells / (step_ms * 1e-3) / 1e6
+    alg_bytes = 2 * Q * STORE_BYTES[storage] * cells  # read + write every population once
+    achieved = alg_bytes / (step_ms * 1e-3) / 1e9
+    kernel = "step"
+    traffic = traffic_from_profile(kernel, args.workload, storage)
+    line = {
+        "metric": METRIC,
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(step_ms, 5),
+        "wall_s_timed": round(wall, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE_NAME[storage],
+        "data": "synthetic (seeded fields of the workload recipe)",
+        "config": {
+            "workload": w["name"],
+            "lattice": "D2Q37" if cfg["lattice"] == 0 else "D3Q39",
+            "grid": [cfg["nx"], cfg["ny"], cfg.get("nz", 1)],
+            "sources": cfg["sources"],
+            "walls": cfg["walls"],
+            "storage": args.storage,
+            "variant": variant,
+            "mass": totals[0],
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "kernel": "whole step (all launches of one time step)",
+            "alg_bytes_per_cell": 2 * Q * STORE_BYTES[storage],
+        },
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(args.workload, storage)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -16,6 +16,8 @@ ARCH = "gfx950"
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
+    # code-object v5 loads on the HIP runtime bundled with PyTorch as well
+    "-mcode-object-version=5",
     # reproducible arithmetic: no implicit contraction (fmaf() is explicit)
     "-ffp-contract=off",
     # no packed FP32 instructions
@@ -53,7 +55,7 @@ def build(verbose=False, jobs=4):
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(compile_one, srcs))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
+    cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-mcode-object-version=5", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (r.stdout, r.stderr))

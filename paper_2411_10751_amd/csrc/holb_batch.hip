@@ -26,6 +26,7 @@ struct RunDesc {
     long long pitch;   // elements per population plane of this run
     long long cell0;   // offset of the run's cells in the theta field
     float omega, kappa, g0, g1, hfac;
+    float rho_ref, thb_ref;
     int pad;
 };
 
@@ -43,6 +44,8 @@ __device__ __forceinline__ KParams run_params(const RunDesc& r, unsigned* err)
     p.omega = r.omega; p.kappa = r.kappa;
     p.g[0] = r.g0; p.g[1] = r.g1; p.g[2] = 0.f;
     p.hfac = r.hfac;
+    p.rho_ref = r.rho_ref;
+    p.thb_ref = r.thb_ref;
     p.err = err;
     return p;
 }
@@ -202,6 +205,8 @@ void plan(holb_batch* b, const holb_config* cfgs, int n)
         const KParams p = params_of(&c);
         d.flags = p.flags;
         d.omega = p.omega; d.kappa = p.kappa; d.g0 = p.g[0]; d.g1 = p.g[1]; d.hfac = p.hfac;
+        d.rho_ref = p.rho_ref;
+        d.thb_ref = p.thb_ref;
         d.pitch = (long long)align_up((size_t)d.N, 64);
         d.off = (long long)elems;
         d.cell0 = (long long)cells;

@@ -54,7 +54,7 @@ __device__ __forceinline__ uint64_t pull_cell(const KParams& p, const typename C
         }
         if (known) {
             const int idx = (sz * p.ny + sy) * p.nx + sx;
-            f[i] = Codec<ST>::dec(fin[(long long)i * p.pitch + idx], LL::w(i), p.ref[i]);
+            f[i] = Codec<ST>::dec(fin[(long long)i * p.pitch + idx], p.dref[i]);
         } else {
             f[i] = 0.0f;
             unk |= 1ull << i;
@@ -70,12 +70,13 @@ __device__ __forceinline__ void wall_coord(const KParams& p, int x, int y, int z
     else { kw = z; nw = p.nz; cil = x + p.nx * y; }
 }
 
-// Pull + wall closure + shifted moments (no stencil force).  Shared by every
-// pass over the state so that they agree bitwise.
+// Pull + wall closure + deviation moments (dr = rho - rho0, j, ed = e -
+// rho0 D c0^2; no stencil force yet).  Shared by every pass over the state so
+// that they agree bitwise.  f holds h_i = f_i / w_i - rho0.
 template <class L, int ST>
 __device__ __forceinline__ void load_state(const KParams& p, const typename Codec<ST>::T* __restrict__ fin,
                                            const float* __restrict__ tgt_in, int x, int y, int z,
-                                           float (&f)[L::Q], float& rho, float (&j)[3], float& e)
+                                           float (&f)[L::Q], float& dr, float (&j)[3], float& ed)
 {
     uint64_t unk = pull_cell<L, ST>(p, fin, x, y, z, f);
     if (p.walls && unk) {
@@ -88,7 +89,7 @@ __device__ __forceinline__ void load_state(const KParams& p, const typename Code
         const int wall = kw == 0 ? 0 : (kw == nw - 1 ? 1 : -1);
         tms_fill<L>(p, f, unk, wall, t);
     }
-    moments<L>(f, rho, j, e);
+    moments<L>(f, dr, j, ed);
 }
 
 // Eq. (3.8): F^SC(x) = -G psi(x) sum_i w_i psi(x + c_i) c_i, FP64, periodic.
@@ -164,8 +165,8 @@ __device__ __forceinline__ void write_targets(const KParams& p, float* __restric
 
 template <class L, int ST, int FAM>
 __device__ __forceinline__ void full_macro(const KParams& p, const float* __restrict__ aux_f,
-                                           const double* __restrict__ aux_d, int x, int y, int z, float rho,
-                                           const float (&j)[3], float e, Macro& m, float& pc)
+                                           const double* __restrict__ aux_d, int x, int y, int z, float dr,
+                                           const float (&j)[3], float ed, Macro& m, float& pc)
 {
     float Fext[3] = {0.f, 0.f, 0.f};
     pc = 0.0f;
@@ -176,7 +177,7 @@ __device__ __forceinline__ void full_macro(const KParams& p, const float* __rest
         for (int a = 0; a < 3; ++a) Fext[a] = (float)Fsc[a];
         pc = ptensor_coef(p, psi_x, Fsc);
     }
-    macro_from_moments<L>(p, rho, j, e, Fext, m);
+    macro_from_moments<L>(p, dr, j, ed, Fext, m);
 }
 
 // One full step of one cell: pull, closure, moments, sources, collision and
@@ -190,11 +191,11 @@ __device__ __forceinline__ void step_cell(const KParams& p, const typename Codec
     using LL = Lat<L>;
     int x, y, z;
     cell_coords<L>(p, cell, x, y, z);
-    float f[L::Q], rho, j[3], e;
-    load_state<L, ST>(p, fin, tgt_in, x, y, z, f, rho, j, e);
+    float f[L::Q], dr, j[3], ed;
+    load_state<L, ST>(p, fin, tgt_in, x, y, z, f, dr, j, ed);
     Macro m;
     float pc;
-    full_macro<L, ST, FAM>(p, aux_f, aux_d, x, y, z, rho, j, e, m, pc);
+    full_macro<L, ST, FAM>(p, aux_f, aux_d, x, y, z, dr, j, ed, m, pc);
     if (p.walls) write_targets<L>(p, tgt_out, x, y, z, m);
     float gT[3] = {0.f, 0.f, 0.f};
     float hc = 0.0f;
@@ -205,7 +206,7 @@ __device__ __forceinline__ void step_cell(const KParams& p, const typename Codec
     collide<L>(p, f, m, hc, gT, pc);
 #pragma unroll
     for (int i = 0; i < L::Q; ++i)
-        fout[(long long)i * p.pitch + cell] = Codec<ST>::enc(f[i], LL::invw(i), p.ref[i]);
+        fout[(long long)i * p.pitch + cell] = Codec<ST>::enc(f[i], p.dref[i]);
 }
 
 // Field pass of one cell: theta (thermal family) or psi (pressure-tensor
@@ -217,17 +218,17 @@ __device__ __forceinline__ void aux_cell(const KParams& p, const typename Codec<
 {
     int x, y, z;
     cell_coords<L>(p, cell, x, y, z);
-    float f[L::Q], rho, j[3], e;
-    load_state<L, ST>(p, fin, tgt_in, x, y, z, f, rho, j, e);
+    float f[L::Q], dr, j[3], ed;
+    load_state<L, ST>(p, fin, tgt_in, x, y, z, f, dr, j, ed);
     if (FAM == FAM_PTENSOR) {
         bool bad = false;
-        aux_d[cell] = psi_vdw(p, (double)rho, L::c0sq, bad);
+        aux_d[cell] = psi_vdw(p, (double)p.rho_ref + (double)dr, L::c0sq, bad);
         if (bad) raise_err(p, HOLB_ERR_EOS_BIT);
     } else {
         const float z3[3] = {0.f, 0.f, 0.f};
         Macro m;
-        macro_from_moments<L>(p, rho, j, e, z3, m);
-        aux_f[cell] = m.theta;
+        macro_from_moments<L>(p, dr, j, ed, z3, m);
+        aux_f[cell] = m.dth;  // theta - theta0: its differences are grad theta
     }
 }
 
@@ -247,6 +248,7 @@ __device__ __forceinline__ void init_cell(const KParams& p, const float* __restr
 #pragma unroll
     for (int a = 0; a < L::D; ++a) m.u[a] = u[(long long)a * p.N + cell];
     m.theta = (p.flags & KF_ISO) ? 1.0f : theta[cell];
+    m.thb = m.theta - 1.0f;
     if (!(m.rho > 0.0f) || !(m.rho < 3.0e38f)) raise_err(p, HOLB_ERR_DENSITY_BIT);
     if (!(m.theta > 0.0f) || !(m.theta < 3.0e38f)) raise_err(p, HOLB_ERR_THETA_BIT);
     if (p.walls) write_targets<L>(p, tgt, x, y, z, m);
@@ -267,8 +269,8 @@ __device__ __forceinline__ void init_cell(const KParams& p, const float* __restr
             else dz = wrapc(dz, p.nz);
         }
         if (!inside) continue;
-        const float fe = feq_one<L>(i, m.rho, m.u, m.theta);
-        fout[(long long)i * p.pitch + (dz * p.ny + dy) * p.nx + dx] = Codec<ST>::enc(fe, LL::invw(i), p.ref[i]);
+        const float fe = feq_dev<L>(p, i, m.rho, m.u, m.thb);
+        fout[(long long)i * p.pitch + (dz * p.ny + dy) * p.nx + dx] = Codec<ST>::enc(fe, p.dref[i]);
     }
 }
 

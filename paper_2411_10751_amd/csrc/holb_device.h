@@ -1,5 +1,13 @@
 // Device-side building blocks of the fused high-order LBM step (gfx950).
 //
+// Populations are handled in deviation form, h_i = f_i / w_i - r_i, with
+// r_i = rho0 (1 + t0_i) the equilibrium bracket of a reference state at rest,
+// f^eq_i(rho0, 0, theta0) / w_i, and t0_i = t_i(u = 0, theta0) of Eq. (2.2).
+// In exact arithmetic this is the same scheme; in FP32 the large constant part
+// cancels exactly instead of being rounded in every collision, which keeps
+// the round-off of density, velocity and temperature at the level of their
+// deviations from the reference.
+//
 // Every kernel variant (generic one-cell-per-thread, plane-marching, batched)
 // calls the same inline functions below, and the library is compiled with
 // -ffp-contract=off and explicit fmaf(), so the per-cell arithmetic -- and
@@ -22,16 +30,24 @@ struct Lat : L {
     static constexpr float invw(int i) { return (float)(1.0 / L::shell_w[L::shell[i]]); }
     static constexpr int c2(int i) { return L::cx[i] * L::cx[i] + L::cy[i] * L::cy[i] + L::cz[i] * L::cz[i]; }
     static constexpr float ic0sq = (float)(1.0 / L::c0sq);
-    static constexpr float c0sq_f = (float)L::c0sq;
+    // D c0^2 (the energy moment of the rest state per unit density)
+    static constexpr float DC = (float)(L::D * L::c0sq);
+    // index of the +e_a velocity (first member of the axis pair of shell 1)
+    static constexpr int axis_plus(int a)
+    {
+        for (int i = 1; i < L::Q; i += 2)
+            if ((a == 0 ? L::cx[i] : a == 1 ? L::cy[i] : L::cz[i]) == 1 && c2(i) == 1) return i;
+        return -1;
+    }
     // opposite index: rest is 0, pairs are (1+2p, 2+2p)
     static constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
-    // velocity component along the wall-normal (last) axis
-    static constexpr int cw(int i) { return L::D == 2 ? L::cy[i] : L::cz[i]; }
 };
 
 // ------------------------------------------------------------------ codec
-// 16-bit storage holds q = f / w - r, r = f^eq_i(reference) / w_i, rounded to
-// nearest-even; decoding is f = w (r + q).
+// FP32 storage holds h_i.  16-bit storage holds q_i = h_i - d_i rounded to
+// nearest-even, where d_i = f^eq_i(rho0, u0, theta0) / w_i - rho0 centres the
+// stored values on the reference state; this is the deviation
+// (f_i - f^eq_i(reference)) / w_i.
 
 template <int ST>
 struct Codec;
@@ -39,21 +55,15 @@ struct Codec;
 template <>
 struct Codec<ST_F32> {
     using T = float;
-    static __device__ __forceinline__ float dec(T v, float, float) { return v; }
-    static __device__ __forceinline__ T enc(float f, float, float) { return f; }
+    static __device__ __forceinline__ float dec(T v, float) { return v; }
+    static __device__ __forceinline__ T enc(float h, float) { return h; }
 };
 
 template <>
 struct Codec<ST_F16> {
     using T = uint16_t;
-    static __device__ __forceinline__ float dec(T v, float w, float r)
-    {
-        return w * (r + (float)__builtin_bit_cast(_Float16, v));
-    }
-    static __device__ __forceinline__ T enc(float f, float invw, float r)
-    {
-        return __builtin_bit_cast(uint16_t, (_Float16)(f * invw - r));
-    }
+    static __device__ __forceinline__ float dec(T v, float d) { return (float)__builtin_bit_cast(_Float16, v) + d; }
+    static __device__ __forceinline__ T enc(float h, float d) { return __builtin_bit_cast(uint16_t, (_Float16)(h - d)); }
 };
 
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f)
@@ -67,14 +77,8 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f)
 template <>
 struct Codec<ST_BF16> {
     using T = uint16_t;
-    static __device__ __forceinline__ float dec(T v, float w, float r)
-    {
-        return w * (r + __uint_as_float((uint32_t)v << 16));
-    }
-    static __device__ __forceinline__ T enc(float f, float invw, float r)
-    {
-        return f32_to_bf16_rne(f * invw - r);
-    }
+    static __device__ __forceinline__ float dec(T v, float d) { return __uint_as_float((uint32_t)v << 16) + d; }
+    static __device__ __forceinline__ T enc(float h, float d) { return f32_to_bf16_rne(h - d); }
 };
 
 // -------------------------------------------------------- small helpers
@@ -93,60 +97,92 @@ __device__ __forceinline__ void raise_err(const KParams& p, unsigned bit)
 
 // ----------------------------------------------------- kinetic algebra
 // Lattice units outside; a = c.u / c0^2, uu = |u|^2 / c0^2, xx = |c|^2 / c0^2
-// are the Hermite-scaled invariants of Eq. (2.2) and Table 2.
+// and thb = theta - 1 are the Hermite-scaled invariants of Eq. (2.2) / Table 2.
 
-// Eq. (2.2) for one direction (used by the wall closure and the
-// initialisation; the collision evaluates it per +/-c pair instead).
-template <class L>
-__device__ __forceinline__ float feq_one(int i, float rho, const float (&u)[3], float theta)
+// Eq. (2.2) for one direction, minus its leading 1: f^eq_i = w_i rho (1 + t).
+template <class L, class R = float>
+__device__ __forceinline__ R feq_t(int i, const float (&uf)[3], float thbf)
 {
     using LL = Lat<L>;
-    constexpr float D = (float)L::D;
-    const float ic = LL::ic0sq;
-    float a = ((float)L::cx[i] * u[0] + (float)L::cy[i] * u[1] + (float)L::cz[i] * u[2]) * ic;
-    float uu = (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) * ic;
-    float xx = (float)LL::c2(i) * ic;
-    float thb = theta - 1.0f;
-    float a2 = a * a;
-    float t = 1.0f + a + 0.5f * a2 - 0.5f * uu + 0.5f * thb * (xx - D)
-            + a2 * a * (1.0f / 6.0f) - 0.5f * a * uu + 0.5f * a * thb * (xx - (D + 2.0f))
-            + a2 * a2 * (1.0f / 24.0f) - 0.25f * a2 * uu + 0.125f * uu * uu
-            + 0.25f * thb * (a2 * (xx - (D + 4.0f)) + uu * ((D + 2.0f) - xx))
-            + 0.125f * thb * thb * (xx * xx - 2.0f * (D + 2.0f) * xx + D * (D + 2.0f));
-    return LL::w(i) * rho * t;
+    constexpr R D = (R)L::D;
+    const R ic = (R)(1.0 / L::c0sq);
+    const R u[3] = {(R)uf[0], (R)uf[1], (R)uf[2]};
+    const R thb = (R)thbf;
+    const R a = ((R)L::cx[i] * u[0] + (R)L::cy[i] * u[1] + (R)L::cz[i] * u[2]) * ic;
+    const R uu = (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) * ic;
+    const R xx = (R)LL::c2(i) * ic;
+    const R a2 = a * a;
+    return a + (R)0.5 * a2 - (R)0.5 * uu + (R)0.5 * thb * (xx - D)
+         + a2 * a * ((R)1 / (R)6) - (R)0.5 * a * uu + (R)0.5 * a * thb * (xx - (D + (R)2))
+         + a2 * a2 * ((R)1 / (R)24) - (R)0.25 * a2 * uu + (R)0.125 * uu * uu
+         + (R)0.25 * thb * (a2 * (xx - (D + (R)4)) + uu * ((D + (R)2) - xx))
+         + (R)0.125 * thb * thb * (xx * xx - (R)2 * (D + (R)2) * xx + D * (D + (R)2));
 }
 
-// Shifted moments of Eq. (4.5): rho = sum f, rho u = sum c f + F/2, and
-// rho D c0^2 theta = sum |c|^2 f - rho |u|^2 + u.F (tr G_2 = 2 u.F).
-struct Macro {
-    float rho, u[3], theta, F[3];
-};
-
+// t0 = t(u = 0, theta0) for a shell of squared speed xx (in c0^2 units).
 template <class L>
-__device__ __forceinline__ void moments(const float (&f)[L::Q], float& rho, float (&j)[3], float& e)
+__device__ __forceinline__ float ref_t0(float xx, float thb0)
+{
+    constexpr float D = (float)L::D;
+    const float q2 = 0.125f * (xx * xx - 2.0f * (D + 2.0f) * xx + D * (D + 2.0f));
+    return thb0 * fmaf(thb0, q2, 0.5f * (xx - D));
+}
+
+// f^eq_i / w_i - r_i (used by the wall closure and the initialisation; the
+// collision evaluates the equilibrium per +/-c pair instead).
+template <class L>
+__device__ __forceinline__ float feq_dev(const KParams& p, int i, float rho, const float (&u)[3], float thb)
 {
     using LL = Lat<L>;
-    rho = 0.f;
+    const float t0 = ref_t0<L>((float)LL::c2(i) * LL::ic0sq, p.thb_ref);
+    return (rho - p.rho_ref) * (1.0f + t0) + rho * (feq_t<L>(i, u, thb) - t0);
+}
+
+// Macroscopic state of a node from the shifted moments of Eq. (4.5):
+// rho = sum f, rho u = sum c f + F/2, and rho D c0^2 theta = sum |c|^2 f -
+// rho |u|^2 + u.F (tr G_2 = 2 u.F).  dr = rho - rho0, dth = theta - theta0,
+// thb = theta - 1; j = sum c f and ed = sum |c|^2 f - rho0 D c0^2 theta0 are
+// kept for the conservation check.
+struct Macro {
+    float rho, dr, u[3], dth, thb, theta, F[3];
+    float j[3], ed;
+};
+
+// Deviation moments from the +/-c pairs: the pair sum carries mass and
+// energy, the pair difference momentum (a difference of two close values is
+// exact, so slow flows keep their full precision).
+template <class L>
+__device__ __forceinline__ void moments(const float (&h)[L::Q], float& dr, float (&j)[3], float& ed)
+{
+    using LL = Lat<L>;
+    dr = LL::w(0) * h[0];
     j[0] = j[1] = j[2] = 0.f;
-    e = 0.f;
+    ed = 0.f;
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-        rho += f[i];
-        if (L::cx[i]) j[0] = fmaf((float)L::cx[i], f[i], j[0]);
-        if (L::cy[i]) j[1] = fmaf((float)L::cy[i], f[i], j[1]);
-        if (L::cz[i]) j[2] = fmaf((float)L::cz[i], f[i], j[2]);
-        if (LL::c2(i)) e = fmaf((float)LL::c2(i), f[i], e);
+    for (int pp = 0; pp < L::NP; ++pp) {
+        const int i = 1 + 2 * pp;
+        const float sm = LL::w(i) * (h[i] + h[i + 1]);
+        const float df = LL::w(i) * (h[i] - h[i + 1]);
+        dr += sm;
+        ed = fmaf((float)LL::c2(i), sm, ed);
+        if (L::cx[i]) j[0] = fmaf((float)L::cx[i], df, j[0]);
+        if (L::cy[i]) j[1] = fmaf((float)L::cy[i], df, j[1]);
+        if (L::cz[i]) j[2] = fmaf((float)L::cz[i], df, j[2]);
     }
 }
 
-template <class L>
-__device__ __forceinline__ void macro_from_moments(const KParams& p, float rho, const float (&j)[3], float e,
+template <class L, bool RAISE = true>
+__device__ __forceinline__ void macro_from_moments(const KParams& p, float dr, const float (&j)[3], float ed,
                                                    const float (&Fext)[3], Macro& m)
 {
-    constexpr float DC = (float)(L::D * L::c0sq);
+    using LL = Lat<L>;
+    const float rho = p.rho_ref + dr;
     m.rho = rho;
+    m.dr = dr;
+    m.ed = ed;
+    m.j[0] = j[0]; m.j[1] = j[1]; m.j[2] = j[2];
     const bool body = p.flags & KF_BODY;
-    float ir = 1.0f / rho;
+    const float ir = 1.0f / rho;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         float F = (body && a < L::D) ? rho * p.g[a] : 0.0f;
@@ -155,27 +191,37 @@ __device__ __forceinline__ void macro_from_moments(const KParams& p, float rho, 
         m.u[a] = (j[a] + 0.5f * F) * ir;
     }
     if (p.flags & KF_ISO) {
+        m.dth = 0.0f;
+        m.thb = 0.0f;
         m.theta = 1.0f;
     } else {
-        float uu = m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2];
-        float uF = m.u[0] * m.F[0] + m.u[1] * m.F[1] + m.u[2] * m.F[2];
-        m.theta = (e - rho * uu + uF) / (rho * DC);
+        const float uu = m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2];
+        const float uF = m.u[0] * m.F[0] + m.u[1] * m.F[1] + m.u[2] * m.F[2];
+        // theta - theta0 = (e - rho |u|^2 + u.F - rho D c0^2 theta0) / (rho D c0^2)
+        const float th0 = 1.0f + p.thb_ref;
+        m.dth = ((ed - dr * (LL::DC * th0)) - rho * uu + uF) / (rho * LL::DC);
+        m.thb = p.thb_ref + m.dth;
+        m.theta = th0 + m.dth;
     }
-    if (!(rho > 0.0f) || !(rho < 3.0e38f)) raise_err(p, HOLB_ERR_DENSITY_BIT);
-    if (!(m.theta > 0.0f) || !(m.theta < 3.0e38f)) raise_err(p, HOLB_ERR_THETA_BIT);
+    if (RAISE) {
+        if (!(rho > 0.0f) || !(rho < 3.0e38f)) raise_err(p, HOLB_ERR_DENSITY_BIT);
+        if (!(m.theta > 0.0f) || !(m.theta < 3.0e38f)) raise_err(p, HOLB_ERR_THETA_BIT);
+    }
 }
 
 // Section 4.3, Eqs. (4.7)-(4.8): rebuild the populations that streamed in
-// from outside the walls.  unk has bit i set for unknown direction i; tgt
-// holds the previous-step (rho, u[D], theta) of this node; wall = 0/1 for a
-// wall node (first/last layer), -1 for a fluid node.
+// from outside the walls, f_i = f_ibar + f^eq_i(tgt) - f^eq_i(loc), where the
+// local state fills the unknown set with the target equilibrium.  unk has bit
+// i set for unknown direction i; tgt holds the previous-step (rho, u[D],
+// theta) of this node; wall = 0/1 for a wall node (first/last layer), -1 for
+// a fluid node, whose target is its own previous-step state.
 template <class L>
-__device__ __forceinline__ void tms_fill(const KParams& p, float (&f)[L::Q], uint64_t unk, int wall,
+__device__ __forceinline__ void tms_fill(const KParams& p, float (&h)[L::Q], uint64_t unk, int wall,
                                          const float* tgt)
 {
     using LL = Lat<L>;
     constexpr int D = L::D;
-    float rt = tgt[0];
+    const float rt = tgt[0];
     float ut[3] = {0.f, 0.f, 0.f};
     float tt;
     if (wall >= 0) {
@@ -188,34 +234,67 @@ __device__ __forceinline__ void tms_fill(const KParams& p, float (&f)[L::Q], uin
         tt = tgt[1 + D];
     }
     if (p.flags & KF_ISO) tt = 1.0f;
-    float rl = 0.f, jl[3] = {0.f, 0.f, 0.f}, el = 0.f;
+    const float tbt = tt - 1.0f;
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-        if ((unk >> i) & 1ull) f[i] = feq_one<L>(i, rt, ut, tt);  // target equilibrium, for now
-        rl += f[i];
-        if (L::cx[i]) jl[0] = fmaf((float)L::cx[i], f[i], jl[0]);
-        if (L::cy[i]) jl[1] = fmaf((float)L::cy[i], f[i], jl[1]);
-        if (L::cz[i]) jl[2] = fmaf((float)L::cz[i], f[i], jl[2]);
-        if (LL::c2(i)) el = fmaf((float)LL::c2(i), f[i], el);
-    }
+    for (int i = 0; i < L::Q; ++i)
+        if ((unk >> i) & 1ull) h[i] = feq_dev<L>(p, i, rt, ut, tbt);  // target equilibrium, for now
+    float drl, jl[3], edl;
+    moments<L>(h, drl, jl, edl);
     const float zero3[3] = {0.f, 0.f, 0.f};
     Macro loc;
-    KParams q = p;
-    q.err = nullptr;
-    macro_from_moments<L>(q, rl, jl, el, zero3, loc);
+    macro_from_moments<L, false>(p, drl, jl, edl, zero3, loc);
+    // the difference of the two equilibria is small next to each of them:
+    // form it in FP64 (wall layers only)
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
-        if ((unk >> i) & 1ull) f[i] = f[LL::opp(i)] + f[i] - feq_one<L>(i, loc.rho, loc.u, loc.theta);
+        if ((unk >> i) & 1ull) {
+            const double et = (double)rt * (1.0 + feq_t<L, double>(i, ut, tbt));
+            const double el = (double)loc.rho * (1.0 + feq_t<L, double>(i, loc.u, loc.thb));
+            h[i] = h[LL::opp(i)] + (float)(et - el);
+        }
     }
 }
 
-// Eq. (4.4) collision with f^eq of Eq. (2.2) and S = F (Eq. 3.3) + H (Eq. 3.7)
-// + P (Eq. 3.12), evaluated once per +/-c pair from its even and odd parts.
+// FP32 compensation of the collision invariants.  In exact arithmetic the
+// collision of Eq. (4.4) maps the moments (rho, j, e) to (rho, j + F,
+// e + 2 u.F) (Eqs. 2.3 and 4.5); with FP32-rounded weights and coefficients
+// the computed post-collision moments miss these by a small systematic
+// amount that would accumulate over many steps.  The residual is put back on
+// the rest population and the +/-e_a axis pairs (|c| = 1), which changes the
+// result only at rounding level.  The energy target applies only when theta
+// is evolved.
+template <class L>
+__device__ __forceinline__ void conserve(const KParams& p, float (&h)[L::Q], const Macro& m)
+{
+    using LL = Lat<L>;
+    constexpr int D = L::D;
+    float dr2, j2[3], e2;
+    moments<L>(h, dr2, j2, e2);
+    const float ddr = m.dr - dr2;
+    float de = 0.0f;
+    if (!(p.flags & KF_ISO)) {
+        const float uF = m.u[0] * m.F[0] + m.u[1] * m.F[1] + m.u[2] * m.F[2];
+        de = fmaf(2.0f, uF, m.ed) - e2;
+    }
+    const float beta = de * (1.0f / (2.0f * D));
+    h[0] += (ddr - de) * LL::invw(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const int ip = LL::axis_plus(a);
+        const float gam = 0.5f * ((m.j[a] + m.F[a]) - j2[a]);
+        h[ip] += (beta + gam) * LL::invw(ip);
+        h[ip + 1] += (beta - gam) * LL::invw(ip);
+    }
+}
+
+// Eq. (4.4) collision, h* = (1 - om) h + om (f^eq / w_i - r_i) + (1 - 1/(2 tau_hat)) S / w_i,
+// with f^eq of Eq. (2.2) and S = F (Eq. 3.3) + H (Eq. 3.7) + P (Eq. 3.12),
+// evaluated once per +/-c pair from its even and odd parts.
 //   hc    = (1 - 1/Pr) rho theta / 2   (0 without the thermal source)
 //   gT    = grad theta per lattice spacing
 //   pc    = -(k / (2 D tau)) |F^SC|^2 / (c0^2 G psi^2)   (0 without it)
 template <class L>
-__device__ __forceinline__ void collide(const KParams& p, float (&f)[L::Q], const Macro& m, float hc,
+__device__ __forceinline__ void collide(const KParams& p, float (&h)[L::Q], const Macro& m, float hc,
                                         const float (&gT)[3], float pc)
 {
     using LL = Lat<L>;
@@ -224,57 +303,64 @@ __device__ __forceinline__ void collide(const KParams& p, float (&f)[L::Q], cons
     const float ic = LL::ic0sq;
     const float uu = (m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2]) * ic;
     const float UF = (m.u[0] * m.F[0] + m.u[1] * m.F[1] + m.u[2] * m.F[2]) * ic;
-    const float thb = m.theta - 1.0f;
+    const float thb = m.thb, dth = m.dth, thb0 = p.thb_ref;
     const float om = p.omega, ka = p.kappa, om1 = 1.0f - p.omega;
     const float orho = om * m.rho;
+    const float odr = om * m.dr;
     const float U[3] = {m.u[0] * ic, m.u[1] * ic, m.u[2] * ic};
     const float Ph[3] = {m.F[0] * ic, m.F[1] * ic, m.F[2] * ic};
 
-    float K0[L::NS], K1[L::NS], K2[L::NS], M1[L::NS], HS[L::NS], PS[L::NS];
-    const float c_uu = 1.0f - 0.5f * uu;
+    // per-shell coefficients of the even (dK0, K2) and odd (K1) parts of the
+    // equilibrium bracket and of the force source (M1); HS, PS of H and P.
+    // dK0 = K0 - (1 + t0) is the even bracket relative to the reference
+    // (thb^2 - thb0^2 = dth (thb + thb0)); R0 = 1 + t0.
+    float dK0[L::NS], R0[L::NS], K1[L::NS], K2[L::NS], M1[L::NS], HS[L::NS], PS[L::NS];
+    const float muu = -0.5f * uu;
 #pragma unroll
     for (int s = 0; s < L::NS; ++s) {
         const float xx = (float)L::shell_c2[s] * ic;
         const float q2 = 0.125f * (xx * xx - 2.0f * (Df + 2.0f) * xx + Df * (Df + 2.0f));
-        K0[s] = c_uu + 0.125f * uu * uu + thb * (0.5f * (xx - Df) + 0.25f * uu * ((Df + 2.0f) - xx) + thb * q2);
-        K1[s] = c_uu + 0.5f * thb * (xx - Df - 2.0f);
+        R0[s] = 1.0f + ref_t0<L>(xx, thb0);
+        dK0[s] = muu + 0.125f * uu * uu + dth * (0.5f * (xx - Df) + q2 * (thb + thb0)) +
+                 thb * 0.25f * uu * ((Df + 2.0f) - xx);
+        K1[s] = 1.0f + muu + 0.5f * thb * (xx - Df - 2.0f);
         K2[s] = 0.5f - 0.25f * uu + 0.25f * thb * (xx - Df - 4.0f);
         M1[s] = 1.0f + 0.5f * (thb * (xx - Df - 2.0f) - uu);
         HS[s] = hc * (xx - Df - 2.0f);
         PS[s] = pc * (xx - Df);
     }
     // rest velocity
-    f[0] = fmaf(om1, f[0], LL::w(0) * fmaf(orho, K0[0], ka * (PS[0] - UF)));
+    h[0] = fmaf(om1, h[0], fmaf(orho, dK0[0], odr * R0[0]) + ka * (PS[0] - UF));
 #pragma unroll
     for (int pp = 0; pp < L::NP; ++pp) {
         const int i = 1 + 2 * pp;
         const int s = L::shell[i];
         constexpr float sixth = 1.0f / 6.0f, c24 = 1.0f / 24.0f;
-        float a = 0.f, b = 0.f, h = 0.f;
-        if (L::cx[i]) { a = fmaf((float)L::cx[i], U[0], a); b = fmaf((float)L::cx[i], Ph[0], b); h = fmaf((float)L::cx[i], gT[0], h); }
-        if (L::cy[i]) { a = fmaf((float)L::cy[i], U[1], a); b = fmaf((float)L::cy[i], Ph[1], b); h = fmaf((float)L::cy[i], gT[1], h); }
-        if (L::cz[i]) { a = fmaf((float)L::cz[i], U[2], a); b = fmaf((float)L::cz[i], Ph[2], b); h = fmaf((float)L::cz[i], gT[2], h); }
+        float a = 0.f, b = 0.f, g = 0.f;
+        if (L::cx[i]) { a = fmaf((float)L::cx[i], U[0], a); b = fmaf((float)L::cx[i], Ph[0], b); g = fmaf((float)L::cx[i], gT[0], g); }
+        if (L::cy[i]) { a = fmaf((float)L::cy[i], U[1], a); b = fmaf((float)L::cy[i], Ph[1], b); g = fmaf((float)L::cy[i], gT[1], g); }
+        if (L::cz[i]) { a = fmaf((float)L::cz[i], U[2], a); b = fmaf((float)L::cz[i], Ph[2], b); g = fmaf((float)L::cz[i], gT[2], g); }
         const float a2 = a * a;
-        const float fe = fmaf(a2, fmaf(a2, c24, K2[s]), K0[s]);
+        const float fe = fmaf(a2, fmaf(a2, c24, K2[s]), dK0[s]);
         const float fo = a * fmaf(a2, sixth, K1[s]);
         const float se = fmaf(a, b, PS[s] - UF);
-        const float so = fmaf(b, fmaf(0.5f, a2, M1[s]), fmaf(HS[s], h, -a * UF));
-        const float E = fmaf(orho, fe, ka * se);
+        const float so = fmaf(b, fmaf(0.5f, a2, M1[s]), fmaf(HS[s], g, -a * UF));
+        const float E = fmaf(orho, fe, odr * R0[s]) + ka * se;
         const float O = fmaf(orho, fo, ka * so);
-        const float w = LL::w(i);
-        f[i] = fmaf(om1, f[i], w * (E + O));
-        f[i + 1] = fmaf(om1, f[i + 1], w * (E - O));
+        h[i] = fmaf(om1, h[i], E + O);
+        h[i + 1] = fmaf(om1, h[i + 1], E - O);
     }
+    conserve<L>(p, h, m);
 }
 
 // van der Waals pseudopotential of Eq. (3.8) in FP64:
 // psi = sqrt(2 (p_EOS - rho c0^2) / (G c0^2)).
 __device__ __forceinline__ double psi_vdw(const KParams& p, double rho, double c0sq, bool& bad)
 {
-    double br = p.eos_b * rho;
+    const double br = p.eos_b * rho;
     if (!(rho > 0.0) || !(br < 1.0)) { bad = true; return 0.0; }
-    double pe = rho * p.eos_T / (1.0 - br) - p.eos_a * rho * rho;
-    double arg = 2.0 * (pe - rho * c0sq) / (p.G * c0sq);
+    const double pe = rho * p.eos_T / (1.0 - br) - p.eos_a * rho * rho;
+    const double arg = 2.0 * (pe - rho * c0sq) / (p.G * c0sq);
     if (!(arg >= 0.0)) { bad = true; return 0.0; }
     return sqrt(arg);
 }

@@ -74,8 +74,10 @@ inline holb_status validate(const holb_config* c)
     }
     if (c->storage < HOLB_STORE_F32 || c->storage > HOLB_STORE_BF16DEV)
         return fail(HOLB_EINVAL, "unknown storage %d", c->storage);
+    if (!(c->rho0 >= 0) || !std::isfinite(c->rho0)) return fail(HOLB_EINVAL, "rho0 must be finite and >= 0");
+    if (!(c->theta0 > 0) || !std::isfinite(c->theta0)) return fail(HOLB_EINVAL, "theta0 must be > 0");
     if (c->storage != HOLB_STORE_F32) {
-        if (!(c->rho0 > 0) || !(c->theta0 > 0) || !std::isfinite(c->rho0) || !std::isfinite(c->theta0))
+        if (!(c->rho0 > 0) || !(c->theta0 > 0) || !std::isfinite(c->theta0))
             return fail(HOLB_EINVAL, "deviation storage needs rho0 > 0 and theta0 > 0");
         for (int a = 0; a < 3; ++a)
             if (!std::isfinite(c->u0[a])) return fail(HOLB_EINVAL, "u0 must be finite");
@@ -117,9 +119,12 @@ inline KParams params_of(const holb_config* c)
         p.pfac = -(c->ptensor_k / (2.0 * D * tau)) / (c0sq * c->sc_G);
         p.eos_a = c->eos_a; p.eos_b = c->eos_b; p.eos_T = c->eos_T; p.G = c->sc_G;
     }
+    p.rho_ref = (float)c->rho0;
+    // the reference temperature only where theta evolves
+    p.thb_ref = c->isothermal ? 0.0f : (float)(c->theta0 - 1.0);
     if (c->storage != HOLB_STORE_F32) {
         double u0[3] = {c->u0[0], c->u0[1], D == 3 ? c->u0[2] : 0.0};
-        deviation_reference(c->lattice, c->rho0, u0, c->theta0, p.ref);
+        deviation_reference(c->lattice, c->rho0, u0, c->isothermal ? 1.0 : c->theta0, p.dref);
     }
     return p;
 }

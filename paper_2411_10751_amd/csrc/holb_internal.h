@@ -36,8 +36,8 @@ hipError_t launch_fields(const LaunchCtx& c, float* rho, float* u, float* theta)
 hipError_t launch_reduce(const LaunchCtx& c, double* out_dev);
 int reduce_blocks(const LaunchCtx& c);
 
-// Reference f^eq_i(rho, u, theta) / w_i of the 16-bit deviation storage, in
-// the library's velocity order (host, FP64 arithmetic of Eq. 2.2).
+// Offset d_i = (f^eq_i(rho, u, theta) - f^eq_i(rho, 0, theta)) / w_i of the
+// 16-bit deviation storage, in the library's velocity order (host, FP64).
 void deviation_reference(int lattice, double rho, const double* u, double theta, float* ref_out);
 
 // Velocity set in library order.

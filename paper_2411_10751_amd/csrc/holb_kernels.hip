@@ -61,11 +61,11 @@ k_fields(const KParams p, const typename Codec<ST>::T* __restrict__ fin, const f
     if (cell >= p.N) return;
     int x, y, z;
     cell_coords<L>(p, cell, x, y, z);
-    float f[L::Q], rho, j[3], e;
-    load_state<L, ST>(p, fin, tgt_in, x, y, z, f, rho, j, e);
+    float f[L::Q], dr, j[3], ed;
+    load_state<L, ST>(p, fin, tgt_in, x, y, z, f, dr, j, ed);
     Macro m;
     float pc;
-    full_macro<L, ST, FAM>(p, aux_f, aux_d, x, y, z, rho, j, e, m, pc);
+    full_macro<L, ST, FAM>(p, aux_f, aux_d, x, y, z, dr, j, ed, m, pc);
     if (rho_out) rho_out[cell] = m.rho;
     if (u_out) {
 #pragma unroll
@@ -94,18 +94,19 @@ k_reduce(const KParams p, const typename Codec<ST>::T* __restrict__ fin, const f
     if (cell < p.N) {
         int x, y, z;
         cell_coords<L>(p, cell, x, y, z);
-        float f[L::Q], rho, j[3], e;
-        load_state<L, ST>(p, fin, tgt_in, x, y, z, f, rho, j, e);
+        float f[L::Q], dr, j[3], ed;
+        load_state<L, ST>(p, fin, tgt_in, x, y, z, f, dr, j, ed);
         Macro m;
         float pc;
-        full_macro<L, ST, FAM>(p, aux_f, aux_d, x, y, z, rho, j, e, m, pc);
-        const double r = m.rho;
+        full_macro<L, ST, FAM>(p, aux_f, aux_d, x, y, z, dr, j, ed, m, pc);
+        // mass from the deviation moment, in FP64
+        const double r = (double)p.rho_ref + (double)m.dr;
         v[0] = r;
         v[1] = r * (double)m.u[0];
         v[2] = r * (double)m.u[1];
         v[3] = r * (double)m.u[2];
         const double uu = (double)m.u[0] * m.u[0] + (double)m.u[1] * m.u[1] + (double)m.u[2] * m.u[2];
-        v[4] = 0.5 * (r * uu + r * (L::D * L::c0sq) * (double)m.theta);
+        v[4] = 0.5 * (r * uu + r * (L::D * L::c0sq) * ((1.0 + (double)p.thb_ref) + (double)m.dth));
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
@@ -295,23 +296,25 @@ void lattice_table(int lattice, int* c, double* w, double* c0sq)
     else table_of<D3Q39>(c, w, c0sq);
 }
 
-// Eq. (2.2) in FP64 on the host, divided by w_i: the reference state of the
-// 16-bit deviation storage.
+// Offset d_i = (f^eq_i(rho0, u0, theta0) - f^eq_i(rho0, 0, theta0)) / w_i of
+// the 16-bit storage (Eq. 2.2 in FP64 on the host), in the library's velocity
+// order: the stored values are then centred on the moving reference state.
 template <class L>
 static void dev_ref(double rho, const double* u, double theta, float* out)
 {
     const double ic = 1.0 / L::c0sq, D = L::D;
-    const double uu = (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) * ic;
     const double thb = theta - 1.0;
+    auto t = [&](double a, double uu, double xx) {
+        return a + 0.5 * a * a - 0.5 * uu + 0.5 * thb * (xx - D) + a * a * a / 6.0 - 0.5 * a * uu +
+               0.5 * a * thb * (xx - (D + 2)) + a * a * a * a / 24.0 - 0.25 * a * a * uu + 0.125 * uu * uu +
+               0.25 * thb * (a * a * (xx - (D + 4)) + uu * ((D + 2) - xx)) +
+               0.125 * thb * thb * (xx * xx - 2.0 * (D + 2) * xx + D * (D + 2));
+    };
+    const double uu = (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) * ic;
     for (int i = 0; i < L::Q; ++i) {
         const double a = (L::cx[i] * u[0] + L::cy[i] * u[1] + L::cz[i] * u[2]) * ic;
         const double xx = (L::cx[i] * L::cx[i] + L::cy[i] * L::cy[i] + L::cz[i] * L::cz[i]) * ic;
-        const double t = 1.0 + a + 0.5 * a * a - 0.5 * uu + 0.5 * thb * (xx - D) + a * a * a / 6.0 -
-                         0.5 * a * uu + 0.5 * a * thb * (xx - (D + 2)) + a * a * a * a / 24.0 -
-                         0.25 * a * a * uu + 0.125 * uu * uu +
-                         0.25 * thb * (a * a * (xx - (D + 4)) + uu * ((D + 2) - xx)) +
-                         0.125 * thb * thb * (xx * xx - 2.0 * (D + 2) * xx + D * (D + 2));
-        out[i] = (float)(rho * t);
+        out[i] = (float)(rho * (t(a, uu, xx) - t(0.0, 0.0, xx)));
     }
 }
 

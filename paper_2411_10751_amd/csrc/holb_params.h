@@ -31,7 +31,9 @@ struct KParams {
     float uwall[2][3];
     double pfac;         // -(k / (2 D tau)) / (c0^2 G), tau = tau_hat - 1/2
     double eos_a, eos_b, eos_T, G;
-    float ref[QMAX];     // f^eq_i(reference) / w_i for the 16-bit storage
+    float rho_ref;       // rho0 and theta0 - 1 of the reference state: populations
+    float thb_ref;       //   are handled as h_i = f_i / w_i - f^eq_i(rho0, 0, theta0) / w_i
+    float dref[QMAX];    // d_i = (f^eq_i(rho0, u0, theta0) - f^eq_i(rho0, 0, theta0)) / w_i (16-bit offset)
     unsigned* err;       // device error word
 };
 

@@ -52,6 +52,12 @@ class HolbError(RuntimeError):
         self.code = code
 
 
+# One HIP runtime per process: PyTorch ships its own libamdhip64 (same soname
+# as the system one).  Importing torch first makes the dynamic linker bind
+# this library to that already-loaded runtime instead of loading a second one,
+# which would not see the GPU that torch has opened.
+import torch  # noqa: E402,F401
+
 if not os.path.exists(LIB_PATH):
     raise ImportError("libholb.so is not built (expected %s); run `python -m "
                       "paper_2411_10751_amd.build` first" % LIB_PATH)

@@ -75,9 +75,19 @@ def rel_errors(gpu, ref, lattice):
     return er, eu, et
 
 
+def where_max(gpu, ref):
+    """Index of the largest absolute error of each field (diagnostics)."""
+    out = []
+    for a, b in zip(gpu, ref):
+        d = np.abs(a - b)
+        out.append(np.unravel_index(int(np.argmax(d)), d.shape))
+    return out
+
+
 def assert_parity(gpu, ref, lattice, tol, what=""):
     e = rel_errors(gpu, ref, lattice)
-    log("%s rel Linf errors rho %.3g u %.3g theta %.3g (tol %.1g)" % (what, e[0], e[1], e[2], tol))
+    log("%s rel Linf errors rho %.3g u %.3g theta %.3g (tol %.1g) at %s" %
+        (what, e[0], e[1], e[2], tol, where_max(gpu, ref)))
     assert max(e) <= tol, (what, e)
     return e
 

@@ -61,7 +61,7 @@ k_batch_aux(const RunDesc* __restrict__ runs, const int2* __restrict__ items, in
         const int cell = t.y + threadIdx.x;
         if (cell < r.N) {
             const KParams p = run_params(r, err);
-            aux_cell<D2Q37, ST_F32, FAM>(p, fin + r.off, tgi, aux + r.cell0, nullptr, cell);
+            aux_cell<D2Q37, ST_F32, FAM, false>(p, fin + r.off, tgi, aux + r.cell0, nullptr, cell);
         }
     }
 }
@@ -78,7 +78,7 @@ k_batch_step(const RunDesc* __restrict__ runs, const int2* __restrict__ items, i
         const int cell = t.y + threadIdx.x;
         if (cell < r.N) {
             const KParams p = run_params(r, err);
-            step_cell<D2Q37, ST_F32, FAM>(p, fin + r.off, fout + r.off, aux + r.cell0, auxd, tgi, tgo, cell);
+            step_cell<D2Q37, ST_F32, FAM, false>(p, fin + r.off, fout + r.off, aux + r.cell0, auxd, tgi, tgo, cell);
         }
     }
 }

@@ -29,12 +29,27 @@ __device__ __forceinline__ void cell_coords(const KParams& p, int cell, int& x, 
 
 // Pull the Q populations of node (x, y, z).  Along the wall-normal axis of a
 // walled domain, sources outside [0, n) are not read; their bits are returned.
-template <class L, int ST>
+// Nodes at least 3 cells from every edge take the source of population i at
+// cell - shift_i with a wave-uniform shift, so that each load is a uniform
+// base plus one shared per-lane offset; the others wrap per coordinate.
+// WALLS = false compiles the periodic pull only (no wall bookkeeping).
+template <class L, int ST, bool WALLS>
 __device__ __forceinline__ uint64_t pull_cell(const KParams& p, const typename Codec<ST>::T* __restrict__ fin,
                                               int x, int y, int z, float (&f)[L::Q])
 {
-    using LL = Lat<L>;
-    const bool walls = p.walls;
+    const bool inner = x >= 3 && x < p.nx - 3 && y >= 3 && y < p.ny - 3 &&
+                       (L::D == 2 || (z >= 3 && z < p.nz - 3));
+    if (inner) {
+        const int cell = (z * p.ny + y) * p.nx + x;
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            const int shift = (L::cz[i] * p.ny + L::cy[i]) * p.nx + L::cx[i];
+            const typename Codec<ST>::T* base = fin + (long long)i * p.pitch - shift;
+            f[i] = Codec<ST>::dec(base[cell], p.dref[i]);
+        }
+        return 0;
+    }
+    const bool walls = WALLS && p.walls;
     int xs[7], ys[7], zs[7];
 #pragma unroll
     for (int k = 0; k < 7; ++k) {
@@ -72,14 +87,15 @@ __device__ __forceinline__ void wall_coord(const KParams& p, int x, int y, int z
 
 // Pull + wall closure + deviation moments (dr = rho - rho0, j, ed = e -
 // rho0 D c0^2; no stencil force yet).  Shared by every pass over the state so
-// that they agree bitwise.  f holds h_i = f_i / w_i - rho0.
-template <class L, int ST>
+// that they agree bitwise.  f holds the deviations h_i.  WALLS = false
+// compiles out the wall closure (periodic domains and interior planes).
+template <class L, int ST, bool WALLS>
 __device__ __forceinline__ void load_state(const KParams& p, const typename Codec<ST>::T* __restrict__ fin,
                                            const float* __restrict__ tgt_in, int x, int y, int z,
                                            float (&f)[L::Q], float& dr, float (&j)[3], float& ed)
 {
-    uint64_t unk = pull_cell<L, ST>(p, fin, x, y, z, f);
-    if (p.walls && unk) {
+    uint64_t unk = pull_cell<L, ST, WALLS>(p, fin, x, y, z, f);
+    if (WALLS && p.walls && unk) {
         int kw, nw, cil;
         wall_coord<L>(p, x, y, z, kw, nw, cil);
         const int slot = wall_slot(kw, nw);
@@ -182,7 +198,7 @@ __device__ __forceinline__ void full_macro(const KParams& p, const float* __rest
 
 // One full step of one cell: pull, closure, moments, sources, collision and
 // store of the post-collision populations at `cell` of fout.
-template <class L, int ST, int FAM>
+template <class L, int ST, int FAM, bool WALLS>
 __device__ __forceinline__ void step_cell(const KParams& p, const typename Codec<ST>::T* __restrict__ fin,
                                           typename Codec<ST>::T* __restrict__ fout, const float* __restrict__ aux_f,
                                           const double* __restrict__ aux_d, const float* __restrict__ tgt_in,
@@ -192,11 +208,11 @@ __device__ __forceinline__ void step_cell(const KParams& p, const typename Codec
     int x, y, z;
     cell_coords<L>(p, cell, x, y, z);
     float f[L::Q], dr, j[3], ed;
-    load_state<L, ST>(p, fin, tgt_in, x, y, z, f, dr, j, ed);
+    load_state<L, ST, WALLS>(p, fin, tgt_in, x, y, z, f, dr, j, ed);
     Macro m;
     float pc;
     full_macro<L, ST, FAM>(p, aux_f, aux_d, x, y, z, dr, j, ed, m, pc);
-    if (p.walls) write_targets<L>(p, tgt_out, x, y, z, m);
+    if (WALLS && p.walls) write_targets<L>(p, tgt_out, x, y, z, m);
     float gT[3] = {0.f, 0.f, 0.f};
     float hc = 0.0f;
     if (FAM == FAM_THERMAL) {
@@ -211,7 +227,7 @@ __device__ __forceinline__ void step_cell(const KParams& p, const typename Codec
 
 // Field pass of one cell: theta (thermal family) or psi (pressure-tensor
 // family) of the current state, read by the stencil of the following pass.
-template <class L, int ST, int FAM>
+template <class L, int ST, int FAM, bool WALLS>
 __device__ __forceinline__ void aux_cell(const KParams& p, const typename Codec<ST>::T* __restrict__ fin,
                                          const float* __restrict__ tgt_in, float* __restrict__ aux_f,
                                          double* __restrict__ aux_d, int cell)
@@ -219,7 +235,7 @@ __device__ __forceinline__ void aux_cell(const KParams& p, const typename Codec<
     int x, y, z;
     cell_coords<L>(p, cell, x, y, z);
     float f[L::Q], dr, j[3], ed;
-    load_state<L, ST>(p, fin, tgt_in, x, y, z, f, dr, j, ed);
+    load_state<L, ST, WALLS>(p, fin, tgt_in, x, y, z, f, dr, j, ed);
     if (FAM == FAM_PTENSOR) {
         bool bad = false;
         aux_d[cell] = psi_vdw(p, (double)p.rho_ref + (double)dr, L::c0sq, bad);

@@ -32,26 +32,41 @@ k_init(const KParams p, const float* __restrict__ rho, const float* __restrict__
     if (cell < p.N) init_cell<L, ST>(p, rho, u, theta, fout, tgt, cell);
 }
 
-template <class L, int ST, int FAM>
-__global__ void __launch_bounds__(GEN_BLOCK)
-k_aux(const KParams p, const typename Codec<ST>::T* __restrict__ fin, const float* __restrict__ tgt_in,
-      float* __restrict__ aux_f, double* __restrict__ aux_d)
+// A set of planes along the last axis, [lo0, lo0 + n0) and [lo1, lo1 + n1):
+// the whole domain, or the layers next to the walls.
+struct PlaneSet {
+    int lo0, n0, lo1, n1;
+};
+
+__device__ __forceinline__ int plane_cell(const KParams& p, const PlaneSet& ps, int c)
 {
-    const int cell = xcd_block() * GEN_BLOCK + threadIdx.x;
-    if (cell < p.N) aux_cell<L, ST, FAM>(p, fin, tgt_in, aux_f, aux_d, cell);
+    const int k = c / p.nlayer, r = c - k * p.nlayer;
+    const int plane = k < ps.n0 ? ps.lo0 + k : ps.lo1 + (k - ps.n0);
+    return plane * p.nlayer + r;
 }
 
-template <class L, int ST, int FAM>
+template <class L, int ST, int FAM, bool WALLS>
 __global__ void __launch_bounds__(GEN_BLOCK)
-k_step(const KParams p, const typename Codec<ST>::T* __restrict__ fin, typename Codec<ST>::T* __restrict__ fout,
-       const float* __restrict__ aux_f, const double* __restrict__ aux_d, const float* __restrict__ tgt_in,
-       float* __restrict__ tgt_out)
+k_aux(const KParams p, const PlaneSet ps, const typename Codec<ST>::T* __restrict__ fin,
+      const float* __restrict__ tgt_in, float* __restrict__ aux_f, double* __restrict__ aux_d)
 {
-    const int cell = xcd_block() * GEN_BLOCK + threadIdx.x;
-    if (cell < p.N) step_cell<L, ST, FAM>(p, fin, fout, aux_f, aux_d, tgt_in, tgt_out, cell);
+    const int c = xcd_block() * GEN_BLOCK + threadIdx.x;
+    if (c < (ps.n0 + ps.n1) * p.nlayer)
+        aux_cell<L, ST, FAM, WALLS>(p, fin, tgt_in, aux_f, aux_d, plane_cell(p, ps, c));
 }
 
-template <class L, int ST, int FAM>
+template <class L, int ST, int FAM, bool WALLS>
+__global__ void __launch_bounds__(GEN_BLOCK)
+k_step(const KParams p, const PlaneSet ps, const typename Codec<ST>::T* __restrict__ fin,
+       typename Codec<ST>::T* __restrict__ fout, const float* __restrict__ aux_f, const double* __restrict__ aux_d,
+       const float* __restrict__ tgt_in, float* __restrict__ tgt_out)
+{
+    const int c = xcd_block() * GEN_BLOCK + threadIdx.x;
+    if (c < (ps.n0 + ps.n1) * p.nlayer)
+        step_cell<L, ST, FAM, WALLS>(p, fin, fout, aux_f, aux_d, tgt_in, tgt_out, plane_cell(p, ps, c));
+}
+
+template <class L, int ST, int FAM, bool WALLS>
 __global__ void __launch_bounds__(GEN_BLOCK)
 k_fields(const KParams p, const typename Codec<ST>::T* __restrict__ fin, const float* __restrict__ aux_f,
          const double* __restrict__ aux_d, const float* __restrict__ tgt_in, float* __restrict__ rho_out,
@@ -62,7 +77,7 @@ k_fields(const KParams p, const typename Codec<ST>::T* __restrict__ fin, const f
     int x, y, z;
     cell_coords<L>(p, cell, x, y, z);
     float f[L::Q], dr, j[3], ed;
-    load_state<L, ST>(p, fin, tgt_in, x, y, z, f, dr, j, ed);
+    load_state<L, ST, WALLS>(p, fin, tgt_in, x, y, z, f, dr, j, ed);
     Macro m;
     float pc;
     full_macro<L, ST, FAM>(p, aux_f, aux_d, x, y, z, dr, j, ed, m, pc);
@@ -83,7 +98,7 @@ __device__ __forceinline__ double wave_sum(double v)
 
 // Block partials of mass, momentum and energy in FP64 (wavefront shuffles,
 // then LDS across the block's waves).
-template <class L, int ST, int FAM>
+template <class L, int ST, int FAM, bool WALLS>
 __global__ void __launch_bounds__(GEN_BLOCK)
 k_reduce(const KParams p, const typename Codec<ST>::T* __restrict__ fin, const float* __restrict__ aux_f,
          const double* __restrict__ aux_d, const float* __restrict__ tgt_in, double* __restrict__ partials)
@@ -95,7 +110,7 @@ k_reduce(const KParams p, const typename Codec<ST>::T* __restrict__ fin, const f
         int x, y, z;
         cell_coords<L>(p, cell, x, y, z);
         float f[L::Q], dr, j[3], ed;
-        load_state<L, ST>(p, fin, tgt_in, x, y, z, f, dr, j, ed);
+        load_state<L, ST, WALLS>(p, fin, tgt_in, x, y, z, f, dr, j, ed);
         Macro m;
         float pc;
         full_macro<L, ST, FAM>(p, aux_f, aux_d, x, y, z, dr, j, ed, m, pc);
@@ -150,6 +165,9 @@ template <class L, int ST, int FAM>
 struct Launch {
     using T = typename Codec<ST>::T;
 
+    static int nm(const KParams& p) { return L::D == 3 ? p.nz : p.ny; }
+    static PlaneSet all(const KParams& p) { return PlaneSet{0, nm(p), 0, 0}; }
+
     static hipError_t init(const LaunchCtx& c, const float* rho, const float* u, const float* th)
     {
         hipLaunchKernelGGL((k_init<L, ST>), dim3(nblocks_for(c.kp.N)), dim3(GEN_BLOCK), 0, c.stream, c.kp, rho, u,
@@ -157,25 +175,68 @@ struct Launch {
         return hipGetLastError();
     }
 
-    static hipError_t aux(const LaunchCtx& c)
+    // walls: the planes need the TMS closure (a wall layer of a walled domain)
+    static hipError_t aux_planes(const LaunchCtx& c, const PlaneSet& ps, bool walls)
     {
         if (FAM == FAM_LOCAL) return hipSuccess;
-        hipLaunchKernelGGL((k_aux<L, ST, FAM>), dim3(nblocks_for(c.kp.N)), dim3(GEN_BLOCK), 0, c.stream, c.kp,
-                           (const T*)c.pop_in, c.tgt_in, c.aux_f, c.aux_d);
+        const int n = (ps.n0 + ps.n1) * c.kp.nlayer;
+        if (n == 0) return hipSuccess;
+        const dim3 grid(nblocks_for(n));
+        if (walls)
+            hipLaunchKernelGGL((k_aux<L, ST, FAM, true>), grid, dim3(GEN_BLOCK), 0, c.stream, c.kp, ps,
+                               (const T*)c.pop_in, c.tgt_in, c.aux_f, c.aux_d);
+        else
+            hipLaunchKernelGGL((k_aux<L, ST, FAM, false>), grid, dim3(GEN_BLOCK), 0, c.stream, c.kp, ps,
+                               (const T*)c.pop_in, c.tgt_in, c.aux_f, c.aux_d);
         return hipGetLastError();
+    }
+
+    static hipError_t step_planes(const LaunchCtx& c, const PlaneSet& ps, bool walls)
+    {
+        const int n = (ps.n0 + ps.n1) * c.kp.nlayer;
+        if (n == 0) return hipSuccess;
+        const dim3 grid(nblocks_for(n));
+        if (walls)
+            hipLaunchKernelGGL((k_step<L, ST, FAM, true>), grid, dim3(GEN_BLOCK), 0, c.stream, c.kp, ps,
+                               (const T*)c.pop_in, (T*)c.pop_out, c.aux_f, c.aux_d, c.tgt_in, c.tgt_out);
+        else
+            hipLaunchKernelGGL((k_step<L, ST, FAM, false>), grid, dim3(GEN_BLOCK), 0, c.stream, c.kp, ps,
+                               (const T*)c.pop_in, (T*)c.pop_out, c.aux_f, c.aux_d, c.tgt_in, c.tgt_out);
+        return hipGetLastError();
+    }
+
+    // Wall layers of a walled domain: the three planes next to each wall.
+    static PlaneSet wall_layers(const KParams& p) { return PlaneSet{0, 3, nm(p) - 3, 3}; }
+    static PlaneSet inner_planes(const KParams& p) { return PlaneSet{3, nm(p) - 6, 0, 0}; }
+
+    static hipError_t aux(const LaunchCtx& c)
+    {
+        if (!c.kp.walls) return aux_planes(c, all(c.kp), false);
+        hipError_t r = aux_planes(c, wall_layers(c.kp), true);
+        if (r == hipSuccess) r = aux_planes(c, inner_planes(c.kp), false);
+        return r;
     }
 
     static hipError_t step(const LaunchCtx& c)
     {
-        if (c.variant != 0) {
-            hipError_t r = march_step<L, ST, FAM>(c);
-            if (r != hipErrorNotSupported) return r;
+        const int n = nm(c.kp);
+        if (c.variant != 0 && march_variant_supported(c, c.variant)) {
+            if (!c.kp.walls) return march_step<L, ST, FAM>(c, 0, n);
+            // wall layers by the generic kernels: theta of the four planes
+            // next to each wall, then the collision of the three wall
+            // layers; the march takes the planes between them and reads the
+            // theta of its two edge planes from the field
+            hipError_t r = aux_planes(c, PlaneSet{0, 4, n - 4, 4}, true);
+            if (r == hipSuccess) r = step_planes(c, wall_layers(c.kp), true);
+            if (r == hipSuccess) r = march_step<L, ST, FAM>(c, 3, n - 3);
+            return r;
         }
         hipError_t r = aux(c);
         if (r != hipSuccess) return r;
-        hipLaunchKernelGGL((k_step<L, ST, FAM>), dim3(nblocks_for(c.kp.N)), dim3(GEN_BLOCK), 0, c.stream, c.kp,
-                           (const T*)c.pop_in, (T*)c.pop_out, c.aux_f, c.aux_d, c.tgt_in, c.tgt_out);
-        return hipGetLastError();
+        if (!c.kp.walls) return step_planes(c, all(c.kp), false);
+        r = step_planes(c, wall_layers(c.kp), true);
+        if (r == hipSuccess) r = step_planes(c, inner_planes(c.kp), false);
+        return r;
     }
 
     static hipError_t fields(const LaunchCtx& c, float* rho, float* u, float* th)
@@ -184,8 +245,12 @@ struct Launch {
             hipError_t r = aux(c);
             if (r != hipSuccess) return r;
         }
-        hipLaunchKernelGGL((k_fields<L, ST, FAM>), dim3(nblocks_for(c.kp.N)), dim3(GEN_BLOCK), 0, c.stream, c.kp,
-                           (const T*)c.pop_in, c.aux_f, c.aux_d, c.tgt_in, rho, u, th);
+        if (c.kp.walls)
+            hipLaunchKernelGGL((k_fields<L, ST, FAM, true>), dim3(nblocks_for(c.kp.N)), dim3(GEN_BLOCK), 0,
+                               c.stream, c.kp, (const T*)c.pop_in, c.aux_f, c.aux_d, c.tgt_in, rho, u, th);
+        else
+            hipLaunchKernelGGL((k_fields<L, ST, FAM, false>), dim3(nblocks_for(c.kp.N)), dim3(GEN_BLOCK), 0,
+                               c.stream, c.kp, (const T*)c.pop_in, c.aux_f, c.aux_d, c.tgt_in, rho, u, th);
         return hipGetLastError();
     }
 
@@ -197,8 +262,12 @@ struct Launch {
         }
         const int nb = nblocks_for(c.kp.N);
         if (nb > c.max_partials) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_reduce<L, ST, FAM>), dim3(nb), dim3(GEN_BLOCK), 0, c.stream, c.kp,
-                           (const T*)c.pop_in, c.aux_f, c.aux_d, c.tgt_in, c.partials);
+        if (c.kp.walls)
+            hipLaunchKernelGGL((k_reduce<L, ST, FAM, true>), dim3(nb), dim3(GEN_BLOCK), 0, c.stream, c.kp,
+                               (const T*)c.pop_in, c.aux_f, c.aux_d, c.tgt_in, c.partials);
+        else
+            hipLaunchKernelGGL((k_reduce<L, ST, FAM, false>), dim3(nb), dim3(GEN_BLOCK), 0, c.stream, c.kp,
+                               (const T*)c.pop_in, c.aux_f, c.aux_d, c.tgt_in, c.partials);
         hipError_t r = hipGetLastError();
         if (r != hipSuccess) return r;
         hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, c.stream, c.partials, nb, out);

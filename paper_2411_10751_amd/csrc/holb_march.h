@@ -10,7 +10,8 @@
 // are now all in LDS.  Every interior population is read once and written
 // once per step; the ring adds (tile + ring) / tile extra reads, which mostly
 // hit L2 because the neighbouring tile pulls the same cells at the same time.
-// Wall planes (TMS, Section 4.3) are handled in the same pass.
+// In a walled domain the layers that need the TMS closure (Section 4.3) are
+// left to the generic kernels and the march covers the planes between them.
 #pragma once
 
 #include "holb_cell.h"
@@ -23,91 +24,157 @@ struct MarchShape {
     static constexpr int TX = TX_, TY = TY_, NCH = NCH_;  // NCH: chunks along the march axis (0 = auto)
 };
 
-template <class L, int ST, class S>
-__global__ void __launch_bounds__(S::TX* S::TY)
-k_march(const KParams p, const typename Codec<ST>::T* __restrict__ fin, typename Codec<ST>::T* __restrict__ fout,
-        const float* __restrict__ tgt_in, float* __restrict__ tgt_out, int ntx, int nty, int nch, int chunk)
+// Work item of a marching workgroup: lateral tile and chunk of planes.
+struct MarchItem {
+    int x, y;        // wrapped lateral coordinates of this thread's column
+    int z0, z1;      // planes [z0, z1) collided by the workgroup
+    bool interior;   // column inside the tile (not the one-cell ring)
+};
+
+template <class L, class S>
+__device__ __forceinline__ MarchItem march_item(const KParams& p, int ntx, int nty, int mlo, int chunk, int mhi)
 {
-    using LL = Lat<L>;
     constexpr bool D3 = L::D == 3;
     constexpr int TX = S::TX, TY = D3 ? S::TY : 1;
     constexpr int IX = TX - 2, IY = D3 ? TY - 2 : 1;
-    __shared__ float th[4][TY][TX];  // theta - theta0 of four consecutive planes
-
+    (void)TY;
     const int tx = threadIdx.x, ty = D3 ? threadIdx.y : 0;
     // XCD-aware order: each XCD gets a contiguous run of (tile, chunk) items.
     const int nb = gridDim.x;
     int b = blockIdx.x;
     if (nb % 8 == 0) b = (b % 8) * (nb / 8) + b / 8;
     const int tile_x = b % ntx;
-    int r = b / ntx;
+    const int r = b / ntx;
     const int tile_y = D3 ? r % nty : 0;
     const int ck = D3 ? r / nty : r;
-    const int nm = D3 ? p.nz : p.ny;  // march extent
-    const int z0 = ck * chunk, z1 = min(z0 + chunk, nm);
-
-    const int gx = tile_x * IX - 1 + tx;            // unwrapped lateral coordinates
+    MarchItem it;
+    it.z0 = mlo + ck * chunk;
+    it.z1 = min(it.z0 + chunk, mhi);
+    const int gx = tile_x * IX - 1 + tx;  // unwrapped lateral coordinates
     const int gy = D3 ? tile_y * IY - 1 + ty : 0;
-    const int x = wrapc(gx, p.nx);
-    const int y = D3 ? wrapc(gy, p.ny) : 0;
-    const bool interior = tx >= 1 && tx <= IX && gx < p.nx && (!D3 || (ty >= 1 && ty <= IY && gy < p.ny));
+    it.x = wrapc(gx, p.nx);
+    it.y = D3 ? wrapc(gy, p.ny) : 0;
+    it.interior = tx >= 1 && tx <= IX && gx < p.nx && (!D3 || (ty >= 1 && ty <= IY && gy < p.ny));
+    return it;
+}
 
-    const bool walls = p.walls;
-    const int pstart = walls ? max(z0 - 1, 0) : z0 - 1;
-    const int pend = walls ? min(z1, nm - 1) : z1;  // last plane pulled
+// theta - theta0 of plane pz into the LDS ring: pulled and reduced to moments,
+// or, for the planes next to the marched range of a walled domain (which need
+// the TMS closure), read from the field the wall pass wrote.
+template <class L, int ST>
+__device__ __forceinline__ float march_theta(const KParams& p, const typename Codec<ST>::T* __restrict__ fin,
+                                             const float* __restrict__ aux_f, int x, int y, int pz, int mlo,
+                                             int mhi, int nm, float (&f)[L::Q])
+{
+    constexpr bool D3 = L::D == 3;
+    if (p.walls && (pz < mlo || pz >= mhi))
+        return aux_f[D3 ? ((long long)pz * p.ny + y) * p.nx + x : (long long)pz * p.nx + x];
+    const int zz = wrapc(pz, nm);
+    float dr, j[3], ed;
+    if (D3) load_state<L, ST, false>(p, fin, nullptr, x, y, zz, f, dr, j, ed);
+    else load_state<L, ST, false>(p, fin, nullptr, x, zz, 0, f, dr, j, ed);
+    const float z3[3] = {0.f, 0.f, 0.f};
+    Macro mq;
+    // flags are raised once, at the collision of the plane
+    macro_from_moments<L, false>(p, dr, j, ed, z3, mq);
+    return mq.dth;
+}
+
+// Collision of plane q of the column from its pulled populations f and the
+// theta ring; writes the post-collision populations.
+template <class L, int ST, int TY, int TX>
+__device__ __forceinline__ void march_collide(const KParams& p, typename Codec<ST>::T* __restrict__ fout,
+                                              const float (&th)[4][TY][TX], int tx, int ty, int x, int y, int q,
+                                              int nm, float (&f)[L::Q])
+{
+    constexpr bool D3 = L::D == 3;
+    const int qq = wrapc(q, nm);
+    float dr, j[3], ed;
+    moments<L>(f, dr, j, ed);
+    const float z3[3] = {0.f, 0.f, 0.f};
+    Macro m;
+    macro_from_moments<L>(p, dr, j, ed, z3, m);
+    float gT[3];
+    gT[0] = 0.5f * (th[q & 3][ty][tx + 1] - th[q & 3][ty][tx - 1]);
+    const float gm = 0.5f * (th[(q + 1) & 3][ty][tx] - th[(q - 1) & 3][ty][tx]);
+    if (D3) {
+        gT[1] = 0.5f * (th[q & 3][ty + 1][tx] - th[q & 3][ty - 1][tx]);
+        gT[2] = gm;
+    } else {
+        gT[1] = gm;
+        gT[2] = 0.0f;
+    }
+    collide<L>(p, f, m, p.hfac * m.rho * m.theta, gT, 0.0f);
+    const long long cell = D3 ? ((long long)qq * p.ny + y) * p.nx + x : (long long)qq * p.nx + x;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) fout[(long long)i * p.pitch + cell] = Codec<ST>::enc(f[i], p.dref[i]);
+}
+
+// Planes [mlo, mhi) are collided; mlo = 0, mhi = nm for a periodic domain.
+// In a walled domain the range excludes the three layers next to each wall,
+// so no pull here needs the TMS closure.
+template <class L, int ST, class S>
+__global__ void __launch_bounds__(S::TX* S::TY)
+k_march(const KParams p, const typename Codec<ST>::T* __restrict__ fin, typename Codec<ST>::T* __restrict__ fout,
+        const float* __restrict__ aux_f, int ntx, int nty, int mlo, int mhi, int chunk)
+{
+    constexpr bool D3 = L::D == 3;
+    constexpr int TX = S::TX, TY = D3 ? S::TY : 1;
+    __shared__ float th[4][TY][TX];  // theta - theta0 of four consecutive planes
+
+    const int tx = threadIdx.x, ty = D3 ? threadIdx.y : 0;
+    const int nm = D3 ? p.nz : p.ny;  // march extent
+    const MarchItem it = march_item<L, S>(p, ntx, nty, mlo, chunk, mhi);
 
     float cur[L::Q], nxt[L::Q];
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) cur[i] = 0.f;
 
-    for (int pz = pstart; pz <= z1; ++pz) {
+    for (int pz = it.z0 - 1; pz <= it.z1; ++pz) {
         // 1. pull plane pz, its theta into the LDS ring
-        if (pz <= pend) {
-            const int zz = walls ? pz : wrapc(pz, nm);
-            float dr, j[3], ed;
-            if (D3) load_state<L, ST>(p, fin, tgt_in, x, y, zz, nxt, dr, j, ed);
-            else load_state<L, ST>(p, fin, tgt_in, x, zz, 0, nxt, dr, j, ed);
-            const float z3[3] = {0.f, 0.f, 0.f};
-            Macro mq;
-            // flags are raised once, at the collision of the plane
-            macro_from_moments<L, false>(p, dr, j, ed, z3, mq);
-            th[pz & 3][ty][tx] = mq.dth;
-        }
+        th[pz & 3][ty][tx] = march_theta<L, ST>(p, fin, aux_f, it.x, it.y, pz, mlo, mhi, nm, nxt);
         __syncthreads();
-        // 2. collide plane q = pz - 1
+        // 2. collide plane q = pz - 1, pulled at the previous iteration
         const int q = pz - 1;
-        if (q >= z0 && interior) {
-            const int qq = walls ? q : wrapc(q, nm);
-            float dr, j[3], ed;
-            moments<L>(cur, dr, j, ed);
-            const float z3[3] = {0.f, 0.f, 0.f};
-            Macro m;
-            macro_from_moments<L>(p, dr, j, ed, z3, m);
-            float gT[3];
-            gT[0] = 0.5f * (th[q & 3][ty][tx + 1] - th[q & 3][ty][tx - 1]);
-            float gm;
-            if (walls && q == 0) gm = th[1][ty][tx] - th[0][ty][tx];
-            else if (walls && q == nm - 1) gm = th[q & 3][ty][tx] - th[(q - 1) & 3][ty][tx];
-            else gm = 0.5f * (th[(q + 1) & 3][ty][tx] - th[(q - 1) & 3][ty][tx]);
-            if (D3) {
-                gT[1] = 0.5f * (th[q & 3][ty + 1][tx] - th[q & 3][ty - 1][tx]);
-                gT[2] = gm;
-            } else {
-                gT[1] = gm;
-                gT[2] = 0.0f;
-            }
-            if (walls) {
-                if (D3) write_targets<L>(p, tgt_out, x, y, qq, m);
-                else write_targets<L>(p, tgt_out, x, qq, 0, m);
-            }
-            collide<L>(p, cur, m, p.hfac * m.rho * m.theta, gT, 0.0f);
-            const int cell = D3 ? (qq * p.ny + y) * p.nx + x : qq * p.nx + x;
-#pragma unroll
-            for (int i = 0; i < L::Q; ++i)
-                fout[(long long)i * p.pitch + cell] = Codec<ST>::enc(cur[i], p.dref[i]);
-        }
+        if (q >= it.z0 && it.interior) march_collide<L, ST, TY, TX>(p, fout, th, tx, ty, it.x, it.y, q, nm, cur);
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) cur[i] = nxt[i];
+    }
+}
+
+// Low-register form: each plane is pulled twice -- once for its theta (the
+// populations are reduced to moments at once), and again one plane later,
+// when it is collided.  The second read follows the first by one plane of the
+// tile, so it is served by L2 or the last-level cache rather than HBM, and
+// only one set of populations is live, which leaves room for more waves per
+// compute unit to hide the latency of the per-plane barrier.
+template <class L, int ST, class S>
+__global__ void __launch_bounds__(S::TX* S::TY)
+k_march2(const KParams p, const typename Codec<ST>::T* __restrict__ fin, typename Codec<ST>::T* __restrict__ fout,
+         const float* __restrict__ aux_f, int ntx, int nty, int mlo, int mhi, int chunk)
+{
+    constexpr bool D3 = L::D == 3;
+    constexpr int TX = S::TX, TY = D3 ? S::TY : 1;
+    __shared__ float th[4][TY][TX];
+
+    const int tx = threadIdx.x, ty = D3 ? threadIdx.y : 0;
+    const int nm = D3 ? p.nz : p.ny;
+    const MarchItem it = march_item<L, S>(p, ntx, nty, mlo, chunk, mhi);
+
+    for (int pz = it.z0 - 1; pz <= it.z1; ++pz) {
+        {
+            float f[L::Q];
+            th[pz & 3][ty][tx] = march_theta<L, ST>(p, fin, aux_f, it.x, it.y, pz, mlo, mhi, nm, f);
+        }
+        __syncthreads();
+        const int q = pz - 1;
+        if (q >= it.z0 && it.interior) {
+            const int qq = wrapc(q, nm);
+            float f[L::Q], dr, j[3], ed;
+            if (D3) load_state<L, ST, false>(p, fin, nullptr, it.x, it.y, qq, f, dr, j, ed);
+            else load_state<L, ST, false>(p, fin, nullptr, it.x, qq, 0, f, dr, j, ed);
+            march_collide<L, ST, TY, TX>(p, fout, th, tx, ty, it.x, it.y, q, nm, f);
+        }
     }
 }
 
@@ -118,15 +185,15 @@ struct MarchVariants;
 
 template <>
 struct MarchVariants<D3Q39> {
-    static constexpr int N = 4;
+    static constexpr int N = 8;
 };
 template <>
 struct MarchVariants<D2Q37> {
-    static constexpr int N = 3;
+    static constexpr int N = 6;
 };
 
-template <class L, int ST, class S>
-inline hipError_t launch_march_shape(const LaunchCtx& c, int chunk_target)
+template <class L, int ST, class S, bool TWICE = false>
+inline hipError_t launch_march_shape(const LaunchCtx& c, int chunk_target, int mlo, int mhi)
 {
     using T = typename Codec<ST>::T;
     constexpr bool D3 = L::D == 3;
@@ -134,12 +201,17 @@ inline hipError_t launch_march_shape(const LaunchCtx& c, int chunk_target)
     const int IX = S::TX - 2, IY = D3 ? S::TY - 2 : 1;
     const int ntx = (p.nx + IX - 1) / IX;
     const int nty = D3 ? (p.ny + IY - 1) / IY : 1;
-    const int nm = D3 ? p.nz : p.ny;
-    const int chunk = chunk_target < nm ? chunk_target : nm;
-    const int nch = (nm + chunk - 1) / chunk;
+    const int nmarch = mhi - mlo;
+    if (nmarch <= 0) return hipSuccess;
+    const int chunk = chunk_target < nmarch ? chunk_target : nmarch;
+    const int nch = (nmarch + chunk - 1) / chunk;
     const dim3 block(S::TX, D3 ? S::TY : 1);
-    hipLaunchKernelGGL((k_march<L, ST, S>), dim3(ntx * nty * nch), block, 0, c.stream, p, (const T*)c.pop_in,
-                       (T*)c.pop_out, c.tgt_in, c.tgt_out, ntx, nty, nch, chunk);
+    if (TWICE)
+        hipLaunchKernelGGL((k_march2<L, ST, S>), dim3(ntx * nty * nch), block, 0, c.stream, p, (const T*)c.pop_in,
+                           (T*)c.pop_out, c.aux_f, ntx, nty, mlo, mhi, chunk);
+    else
+        hipLaunchKernelGGL((k_march<L, ST, S>), dim3(ntx * nty * nch), block, 0, c.stream, p, (const T*)c.pop_in,
+                           (T*)c.pop_out, c.aux_f, ntx, nty, mlo, mhi, chunk);
     return hipGetLastError();
 }
 
@@ -159,22 +231,31 @@ inline bool march_variant_supported(const LaunchCtx& c, int v)
     return v <= MarchVariants<D2Q37>::N && nlat >= 2 && nm >= 1;
 }
 
+// Collide planes [mlo, mhi) along the last axis with the marching kernel of
+// the context's variant.
 template <class L, int ST, int FAM>
-hipError_t march_step(const LaunchCtx& c)
+hipError_t march_step(const LaunchCtx& c, int mlo, int mhi)
 {
     if (FAM != FAM_THERMAL || !march_variant_supported(c, c.variant)) return hipErrorNotSupported;
     if constexpr (L::D == 3) {
         switch (c.variant) {
-        case 1: return launch_march_shape<L, ST, MarchShape<34, 18, 0>>(c, 64);
-        case 2: return launch_march_shape<L, ST, MarchShape<34, 18, 0>>(c, 32);
-        case 3: return launch_march_shape<L, ST, MarchShape<66, 10, 0>>(c, 64);
-        case 4: return launch_march_shape<L, ST, MarchShape<18, 34, 0>>(c, 64);
+        case 1: return launch_march_shape<L, ST, MarchShape<34, 18, 0>>(c, 64, mlo, mhi);
+        case 2: return launch_march_shape<L, ST, MarchShape<34, 18, 0>>(c, 32, mlo, mhi);
+        case 3: return launch_march_shape<L, ST, MarchShape<66, 10, 0>>(c, 64, mlo, mhi);
+        case 4: return launch_march_shape<L, ST, MarchShape<18, 34, 0>>(c, 64, mlo, mhi);
+        case 5: return launch_march_shape<L, ST, MarchShape<34, 18, 0>, true>(c, 64, mlo, mhi);
+        case 6: return launch_march_shape<L, ST, MarchShape<66, 10, 0>, true>(c, 64, mlo, mhi);
+        case 7: return launch_march_shape<L, ST, MarchShape<34, 10, 0>, true>(c, 64, mlo, mhi);
+        case 8: return launch_march_shape<L, ST, MarchShape<66, 6, 0>, true>(c, 64, mlo, mhi);
         }
     } else {
         switch (c.variant) {
-        case 1: return launch_march_shape<L, ST, MarchShape<258, 1, 0>>(c, 32);
-        case 2: return launch_march_shape<L, ST, MarchShape<130, 1, 0>>(c, 32);
-        case 3: return launch_march_shape<L, ST, MarchShape<130, 1, 0>>(c, 64);
+        case 1: return launch_march_shape<L, ST, MarchShape<258, 1, 0>>(c, 32, mlo, mhi);
+        case 2: return launch_march_shape<L, ST, MarchShape<130, 1, 0>>(c, 32, mlo, mhi);
+        case 3: return launch_march_shape<L, ST, MarchShape<130, 1, 0>>(c, 64, mlo, mhi);
+        case 4: return launch_march_shape<L, ST, MarchShape<258, 1, 0>, true>(c, 32, mlo, mhi);
+        case 5: return launch_march_shape<L, ST, MarchShape<130, 1, 0>, true>(c, 32, mlo, mhi);
+        case 6: return launch_march_shape<L, ST, MarchShape<66, 1, 0>, true>(c, 64, mlo, mhi);
         }
     }
     return hipErrorNotSupported;

@@ -232,7 +232,8 @@ def test_reduce_deterministic_and_matches_fields():
     assert np.array_equal(a, b)  # bitwise repeatable
     r, u, t = [x.cpu().numpy().astype(np.float64) for x in sim.fields()]
     mass = math.fsum(r.ravel())
-    assert abs(a[0] - mass) <= 1e-13 * mass
+    # the fields are rounded to FP32 cell by cell: |sum fl(r) - sum r| <= 2^-24 sum r
+    assert abs(a[0] - mass) <= 2.0 ** -24 * mass
     px = math.fsum((r * u[0]).ravel())
     assert abs(a[1] - px) <= 1e-6 * abs(px) + 1e-9
     o = run_oracle(w["config"], w["rho"], w["u"], w["theta"], 20)

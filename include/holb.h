@@ -158,6 +158,20 @@ holb_status holb_tune(holb_sim* s, int32_t* variant_out);
 holb_status holb_set_variant(holb_sim* s, int32_t variant);
 holb_status holb_num_variants(holb_sim* s, int32_t* n);
 
+/* Instrumentation.  holb_timing_start makes each of the next max_steps
+ * (1..100000) steps record a pair of HIP events on the library's stream
+ * around the step's dominant kernel (the collision of the cells away from the
+ * wall layers; in a periodic domain, of every cell).  holb_timing_stop
+ * synchronises on the last event and returns the summed kernel time in ms,
+ * the number of timed launches, the cells one launch updates and the kernel's
+ * name as a profiler lists it, without namespace and spaces (written to
+ * kernel, at most kernel_len bytes with the terminator; any output may be
+ * NULL).  Steps beyond max_steps run untimed; holb_timing_start again
+ * discards the events of an unfinished timing. */
+holb_status holb_timing_start(holb_sim* s, int32_t max_steps);
+holb_status holb_timing_stop(holb_sim* s, double* kernel_ms, int64_t* launches, int64_t* cells_per_launch,
+                             char* kernel, size_t kernel_len);
+
 holb_status holb_destroy(holb_sim* s);
 
 /* ---- Batched form: many independent periodic D2Q37 runs in one launch ---- */

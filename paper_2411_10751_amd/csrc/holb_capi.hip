@@ -78,6 +78,16 @@ struct holb_sim {
     bool initialized = false;
     int variant = 0;
     LaunchCtx base;
+    std::vector<hipEvent_t> timing;  // event pairs of the timed steps
+    size_t timed = 0;                // pairs recorded so far
+
+    void drop_timing()
+    {
+        for (hipEvent_t e : timing) (void)hipEventDestroy(e);
+        timing.clear();
+        timed = 0;
+    }
+    ~holb_sim() { drop_timing(); }
 
     LaunchCtx ctx(bool advance) const
     {
@@ -186,7 +196,13 @@ holb_status holb_step(holb_sim* s, int64_t n)
     if (n < 0) return fail(HOLB_EINVAL, "n must be >= 0");
     if (!s->initialized) return fail(HOLB_ESTATE, "holb_step before holb_init");
     for (int64_t k = 0; k < n; ++k) {
-        hipError_t e = launch_step(s->ctx(true));
+        LaunchCtx c = s->ctx(true);
+        if (2 * (s->timed + 1) <= s->timing.size()) {
+            c.ev_begin = s->timing[2 * s->timed];
+            c.ev_end = s->timing[2 * s->timed + 1];
+            ++s->timed;
+        }
+        hipError_t e = launch_step(c);
         if (e != hipSuccess) return hip_fail(e, "step kernel");
         s->cur = 1 - s->cur;
     }
@@ -302,6 +318,47 @@ holb_status holb_tune(holb_sim* s, int32_t* variant_out)
     if (e != hipSuccess) return hip_fail(e, "tuning");
     s->variant = best;
     if (variant_out) *variant_out = best;
+    return HOLB_OK;
+}
+
+holb_status holb_timing_start(holb_sim* s, int32_t max_steps)
+{
+    if (!s) return fail(HOLB_EINVAL, "handle is NULL");
+    if (max_steps < 1 || max_steps > 100000) return fail(HOLB_EINVAL, "max_steps must be in [1, 100000]");
+    s->drop_timing();
+    s->timing.resize(2 * (size_t)max_steps, nullptr);
+    for (auto& ev : s->timing) {
+        hipError_t e = hipEventCreate(&ev);
+        if (e != hipSuccess) {
+            ev = nullptr;
+            s->drop_timing();
+            return hip_fail(e, "hipEventCreate");
+        }
+    }
+    return HOLB_OK;
+}
+
+holb_status holb_timing_stop(holb_sim* s, double* kernel_ms, int64_t* launches, int64_t* cells_per_launch,
+                             char* kernel, size_t kernel_len)
+{
+    if (!s) return fail(HOLB_EINVAL, "handle is NULL");
+    double total = 0.0;
+    hipError_t e = hipSuccess;
+    if (s->timed) e = hipEventSynchronize(s->timing[2 * s->timed - 1]);
+    for (size_t k = 0; k < s->timed && e == hipSuccess; ++k) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, s->timing[2 * k], s->timing[2 * k + 1]);
+        total += ms;
+    }
+    const int64_t n = (int64_t)s->timed;
+    s->drop_timing();
+    if (e != hipSuccess) return hip_fail(e, "reading the timing events");
+    long long cells = 0;
+    LaunchCtx c = s->ctx(true);
+    dominant_kernel(c, kernel, kernel_len, &cells);
+    if (kernel_ms) *kernel_ms = total;
+    if (launches) *launches = n;
+    if (cells_per_launch) *cells_per_launch = cells;
     return HOLB_OK;
 }
 

@@ -24,6 +24,8 @@ struct LaunchCtx {
     double* partials;     // reduction partials
     int max_partials;     // capacity in blocks
     hipStream_t stream;
+    hipEvent_t ev_begin;  // if set, recorded around the dominant kernel of a step
+    hipEvent_t ev_end;
 };
 
 int num_variants(const LaunchCtx& c);
@@ -35,6 +37,11 @@ hipError_t launch_aux(const LaunchCtx& c);  // psi / theta field of the current 
 hipError_t launch_fields(const LaunchCtx& c, float* rho, float* u, float* theta);
 hipError_t launch_reduce(const LaunchCtx& c, double* out_dev);
 int reduce_blocks(const LaunchCtx& c);
+
+// Dominant kernel of one step (the one bracketed by ev_begin / ev_end): its
+// name as a profiler lists it, without namespace and spaces, and the number
+// of cells one launch updates.
+void dominant_kernel(const LaunchCtx& c, char* name, size_t len, long long* cells);
 
 // Offset d_i = (f^eq_i(rho, u, theta) - f^eq_i(rho, 0, theta)) / w_i of the
 // 16-bit deviation storage, in the library's velocity order (host, FP64).

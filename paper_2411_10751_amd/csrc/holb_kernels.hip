@@ -11,6 +11,7 @@
 // sources (temperature gradient, pseudopotential force) read a field written
 // by a preceding pass over the same state (launch_aux).
 #include <hip/hip_runtime.h>
+#include <stdio.h>
 
 #include "holb_cell.h"
 #include "holb_device.h"
@@ -217,26 +218,53 @@ struct Launch {
         return r;
     }
 
+    static hipError_t mark(const LaunchCtx& c, hipEvent_t e)
+    {
+        return e ? hipEventRecord(e, c.stream) : hipSuccess;
+    }
+
+    // The dominant launch of a step between the two timing events.
+    template <class F>
+    static hipError_t timed(const LaunchCtx& c, F&& launch)
+    {
+        hipError_t r = mark(c, c.ev_begin);
+        if (r == hipSuccess) r = launch();
+        if (r == hipSuccess) r = mark(c, c.ev_end);
+        return r;
+    }
+
     static hipError_t step(const LaunchCtx& c)
     {
         const int n = nm(c.kp);
         if (c.variant != 0 && march_variant_supported(c, c.variant)) {
-            if (!c.kp.walls) return march_step<L, ST, FAM>(c, 0, n);
+            if (!c.kp.walls) return timed(c, [&] { return march_step<L, ST, FAM>(c, 0, n); });
             // wall layers by the generic kernels: theta of the four planes
             // next to each wall, then the collision of the three wall
             // layers; the march takes the planes between them and reads the
             // theta of its two edge planes from the field
             hipError_t r = aux_planes(c, PlaneSet{0, 4, n - 4, 4}, true);
             if (r == hipSuccess) r = step_planes(c, wall_layers(c.kp), true);
-            if (r == hipSuccess) r = march_step<L, ST, FAM>(c, 3, n - 3);
+            if (r == hipSuccess) r = timed(c, [&] { return march_step<L, ST, FAM>(c, 3, n - 3); });
             return r;
         }
         hipError_t r = aux(c);
         if (r != hipSuccess) return r;
-        if (!c.kp.walls) return step_planes(c, all(c.kp), false);
+        if (!c.kp.walls) return timed(c, [&] { return step_planes(c, all(c.kp), false); });
         r = step_planes(c, wall_layers(c.kp), true);
-        if (r == hipSuccess) r = step_planes(c, inner_planes(c.kp), false);
+        if (r == hipSuccess) r = timed(c, [&] { return step_planes(c, inner_planes(c.kp), false); });
         return r;
+    }
+
+    static void dominant(const LaunchCtx& c, char* name, size_t len, long long* cells)
+    {
+        const int n = nm(c.kp);
+        const bool march = c.variant != 0 && march_variant_supported(c, c.variant);
+        const int planes = c.kp.walls ? n - 6 : n;
+        if (cells) *cells = (long long)planes * c.kp.nlayer;
+        if (!name || !len) return;
+        const char* lat = L::D == 3 ? "D3Q39" : "D2Q37";
+        if (march) march_kernel_name<L>(c.variant, lat, ST, name, len);
+        else snprintf(name, len, "k_step<%s,%d,%d,false>", lat, ST, FAM);
     }
 
     static hipError_t fields(const LaunchCtx& c, float* rho, float* u, float* th)
@@ -332,6 +360,32 @@ hipError_t launch_reduce(const LaunchCtx& c, double* out_dev)
     return dispatch(c, 4, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, out_dev);
 }
 int reduce_blocks(const LaunchCtx& c) { return nblocks_for(c.kp.N); }
+
+template <class L, int ST>
+static void dominant_family(const LaunchCtx& c, char* name, size_t len, long long* cells)
+{
+    switch (c.family) {
+    case FAM_LOCAL: Launch<L, ST, FAM_LOCAL>::dominant(c, name, len, cells); break;
+    case FAM_THERMAL: Launch<L, ST, FAM_THERMAL>::dominant(c, name, len, cells); break;
+    default: Launch<L, ST, FAM_PTENSOR>::dominant(c, name, len, cells); break;
+    }
+}
+
+template <class L>
+static void dominant_storage(const LaunchCtx& c, char* name, size_t len, long long* cells)
+{
+    switch (c.storage) {
+    case ST_F32: dominant_family<L, ST_F32>(c, name, len, cells); break;
+    case ST_F16: dominant_family<L, ST_F16>(c, name, len, cells); break;
+    default: dominant_family<L, ST_BF16>(c, name, len, cells); break;
+    }
+}
+
+void dominant_kernel(const LaunchCtx& c, char* name, size_t len, long long* cells)
+{
+    if (c.lattice == 0) dominant_storage<D2Q37>(c, name, len, cells);
+    else dominant_storage<D3Q39>(c, name, len, cells);
+}
 
 int num_variants(const LaunchCtx& c) { return 1 + march_num_variants(c); }
 

@@ -14,6 +14,8 @@
 // left to the generic kernels and the march covers the planes between them.
 #pragma once
 
+#include <stdio.h>
+
 #include "holb_cell.h"
 #include "holb_internal.h"
 
@@ -229,6 +231,20 @@ inline bool march_variant_supported(const LaunchCtx& c, int v)
     // a tile must not cover a periodic lateral axis more than once
     if (c.lattice == 1) return v <= MarchVariants<D3Q39>::N && nlat >= 2 && c.kp.ny >= 2 && nm >= 1;
     return v <= MarchVariants<D2Q37>::N && nlat >= 2 && nm >= 1;
+}
+
+// Kernel name of a variant, as a profiler lists it without namespace and
+// spaces (shapes as in march_step).
+template <class L>
+inline void march_kernel_name(int v, const char* lat, int st, char* name, size_t len)
+{
+    static const int s3[9][3] = {{0, 0, 0}, {34, 18, 0}, {34, 18, 0}, {66, 10, 0}, {18, 34, 0},
+                                 {34, 18, 1}, {66, 10, 1}, {34, 10, 1}, {66, 6, 1}};
+    static const int s2[7][2] = {{0, 0}, {258, 0}, {130, 0}, {130, 0}, {258, 1}, {130, 1}, {66, 1}};
+    int tx, ty, twice;
+    if (L::D == 3) { tx = s3[v][0]; ty = s3[v][1]; twice = s3[v][2]; }
+    else { tx = s2[v][0]; ty = 1; twice = s2[v][1]; }
+    snprintf(name, len, "%s<%s,%d,MarchShape<%d,%d,0>>", twice ? "k_march2" : "k_march", lat, st, tx, ty);
 }
 
 // Collide planes [mlo, mhi) along the last axis with the marching kernel of

@@ -82,6 +82,9 @@ _sig = {
     "holb_set_state": ([_vp, _vp, ctypes.c_size_t], ctypes.c_int32),
     "holb_tune": ([_vp, _P(ctypes.c_int32)], ctypes.c_int32),
     "holb_set_variant": ([_vp, ctypes.c_int32], ctypes.c_int32),
+    "holb_timing_start": ([_vp, ctypes.c_int32], ctypes.c_int32),
+    "holb_timing_stop": ([_vp, _P(ctypes.c_double), _P(ctypes.c_int64), _P(ctypes.c_int64), ctypes.c_char_p,
+                          ctypes.c_size_t], ctypes.c_int32),
     "holb_num_variants": ([_vp, _P(ctypes.c_int32)], ctypes.c_int32),
     "holb_destroy": ([_vp], ctypes.c_int32),
     "holb_batch_workspace_size": ([_P(holb_config), ctypes.c_int32, _P(ctypes.c_size_t)], ctypes.c_int32),
@@ -268,6 +271,20 @@ class Sim:
         n = ctypes.c_int32()
         check(holb_num_variants(self._h, ctypes.byref(n)), "holb_num_variants")
         return n.value
+
+    def timing_start(self, max_steps):
+        check(holb_timing_start(self._h, int(max_steps)), "holb_timing_start")
+
+    def timing_stop(self):
+        """(summed ms, launches, cells per launch, kernel name) of the dominant
+        kernel over the steps timed since timing_start."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        cells = ctypes.c_int64()
+        name = ctypes.create_string_buffer(256)
+        check(holb_timing_stop(self._h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(cells), name, 256),
+              "holb_timing_stop")
+        return ms.value, n.value, cells.value, name.value.decode()
 
 
 class Batch:

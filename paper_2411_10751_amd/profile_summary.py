@@ -1,0 +1,161 @@
+"""Summaries of rocprofv3 output for the bench workloads (CPU only).
+
+    python -m paper_2411_10751_amd.profile_summary kernels DIR OUT.md  --cmd "..."
+    python -m paper_2411_10751_amd.profile_summary traffic FETCH_DIR WRITE_DIR OUT.txt --kernel NAME
+           --cells N --bytes-per-cell B --cmd "..." --cmd "..."
+
+`kernels` condenses the kernel statistics of a `--kernel-trace --stats`
+run (CSV output) into a table.  `traffic` reads two `--pmc` runs, one with
+FETCH_SIZE and one with WRITE_SIZE (KiB per dispatch), takes the mean of the
+named kernel's dispatches, and scales each counter by what it reads for the
+reference streaming dispatch of known size that bench.py issues with
+--copy-calibration (an elementwise negation of 2^28 float32 values: 1 GiB read,
+1 GiB written).  The result is HBM bytes per launch, stamped with a hash of the
+kernel sources so that bench.py ignores it once the kernels have changed.
+"""
+import argparse
+import csv
+import glob
+import hashlib
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CALIB_BYTES = 1 << 30
+
+
+def source_sha256():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2411_10751_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()
+
+
+def short_name(name):
+    """Kernel name without the library namespace, argument list and spaces."""
+    n = name.strip()
+    if n.startswith("void "):
+        n = n[5:]
+    # drop the parameter list: the last top-level parenthesised group
+    depth = 0
+    for k, ch in enumerate(n):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            n = n[:k]
+            break
+    n = n.replace("holb::", "").replace(" ", "")
+    return n
+
+
+def _csv(dirname, suffix):
+    files = sorted(glob.glob(os.path.join(dirname, "**", "*" + suffix), recursive=True))
+    if not files:
+        raise SystemExit("no *%s under %s" % (suffix, dirname))
+    rows = []
+    for f in files:
+        with open(f, newline="") as fh:
+            rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def kernels(args):
+    rows = _csv(args.dir, "kernel_stats.csv")
+    total = sum(float(r["TotalDurationNs"]) for r in rows)
+    out = ["# Kernel time, %s" % args.title, "", "Command (from the repository root):", "",
+           "    " + args.cmd, "",
+           "| kernel | calls | average us | min us | max us | share of GPU time |",
+           "|---|---|---|---|---|---|"]
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    for r in rows[: args.top]:
+        out.append("| `%s` | %s | %.2f | %.2f | %.2f | %.1f%% |" % (
+            short_name(r["Name"]), r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
+            float(r["MaxNs"]) / 1e3, 100.0 * float(r["TotalDurationNs"]) / total))
+    open(args.out, "w").write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
+def _counter_means(dirname, counter):
+    """{short kernel name: mean counter value per dispatch} of one pmc run."""
+    rows = _csv(dirname, "counter_collection.csv")
+    acc = {}
+    for r in rows:
+        if r.get("Counter_Name") != counter:
+            continue
+        k = short_name(r["Kernel_Name"])
+        s, n = acc.get(k, (0.0, 0))
+        acc[k] = (s + float(r["Counter_Value"]), n + 1)
+    return {k: s / n for k, (s, n) in acc.items()}
+
+
+def _calibration(means):
+    cands = [k for k in means if re.search(r"neg", k)]
+    if not cands:
+        raise SystemExit("no calibration dispatch (elementwise negation) in the counter output")
+    return max(means[k] for k in cands)
+
+
+def traffic(args):
+    fetch = _counter_means(args.fetch_dir, "FETCH_SIZE")
+    write = _counter_means(args.write_dir, "WRITE_SIZE")
+    key = args.kernel.replace(" ", "")
+    fk = [k for k in fetch if k == key]
+    wk = [k for k in write if k == key]
+    if not fk or not wk:
+        raise SystemExit("kernel %s not in the counter output (have: %s)" % (key, sorted(fetch)))
+    f_kib, w_kib = fetch[fk[0]], write[wk[0]]
+    cf_kib, cw_kib = _calibration(fetch), _calibration(write)
+    f_scale = CALIB_BYTES / (cf_kib * 1024.0)
+    w_scale = CALIB_BYTES / (cw_kib * 1024.0)
+    hbm = f_kib * 1024.0 * f_scale + w_kib * 1024.0 * w_scale
+    alg = args.cells * args.bytes_per_cell
+    lines = [
+        "# HBM traffic per launch of the dominant kernel, %s" % args.title,
+        "# Commands (from the repository root), one rocprofv3 pass per counter:",
+    ] + ["#   " + c for c in args.cmd] + [
+        "# Counters are KiB per dispatch; each is scaled by its reading for the",
+        "# calibration dispatch (elementwise negation of 2^28 float32: 1 GiB read, 1 GiB written).",
+        "kernel: %s" % key,
+        "source_sha256: %s" % source_sha256(),
+        "fetch_kib_per_dispatch: %.1f" % f_kib,
+        "write_kib_per_dispatch: %.1f" % w_kib,
+        "calibration_fetch_kib: %.1f" % cf_kib,
+        "calibration_write_kib: %.1f" % cw_kib,
+        "fetch_scale: %.5f" % f_scale,
+        "write_scale: %.5f" % w_scale,
+        "hbm_bytes_per_launch: %.0f" % hbm,
+        "algorithmic_bytes_per_launch: %d" % alg,
+        "traffic_over_algorithmic: %.4f" % (hbm / alg),
+    ]
+    open(args.out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="what", required=True)
+    k = sub.add_parser("kernels")
+    k.add_argument("dir")
+    k.add_argument("out")
+    k.add_argument("--cmd", required=True)
+    k.add_argument("--title", default="")
+    k.add_argument("--top", type=int, default=12)
+    t = sub.add_parser("traffic")
+    t.add_argument("fetch_dir")
+    t.add_argument("write_dir")
+    t.add_argument("out")
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--cells", type=int, required=True)
+    t.add_argument("--bytes-per-cell", type=int, required=True)
+    t.add_argument("--cmd", action="append", required=True)
+    t.add_argument("--title", default="")
+    args = ap.parse_args()
+    kernels(args) if args.what == "kernels" else traffic(args)
+
+
+if __name__ == "__main__":
+    main()

@@ -62,9 +62,12 @@ typedef int32_t holb_status;
 #define HOLB_SRC_THERMAL 2u /* thermal-dissipation source H_i, Eq. (3.7) */
 #define HOLB_SRC_PTENSOR 4u /* pseudopotential force (Eq. 3.8) + P_i (Eq. 3.12) */
 
-/* Population storage in device memory.  Arithmetic is always FP32.  The
- * 16-bit forms store q_i = (f_i - f^eq_i(rho0, u0, theta0)) / w_i, rounded to
- * nearest-even, and decode f_i = w_i (q_i + f^eq_i(ref) / w_i). */
+/* Population storage in device memory.  Arithmetic is always FP32.  Every
+ * cell carries a frame (its density and temperature of the last step, rounded
+ * to binary16), and populations are stored as deviations from the rest
+ * equilibrium of their cell's frame, divided by w_i.  The 16-bit forms also
+ * subtract the bracket of the uniform background velocity u0 and round to
+ * nearest-even (see holb_get_state for the exact format). */
 #define HOLB_STORE_F32 0
 #define HOLB_STORE_F16DEV 1
 #define HOLB_STORE_BF16DEV 2
@@ -87,7 +90,9 @@ typedef struct {
     double sc_G;          /* pseudopotential coupling G (the paper uses -1) */
     double ptensor_k;     /* free parameter k of P_i, Eq. (3.12) */
     int32_t storage;      /* HOLB_STORE_* */
-    double rho0, theta0, u0[3]; /* reference state of the 16-bit deviation storage */
+    double rho0, theta0, u0[3]; /* background state: u0 (with rho0, theta0) centres the 16-bit
+                                 * storage; theta0 is the offset of the temperature field of
+                                 * the gradient stencil */
     int32_t walls;        /* 0: periodic; 1: TMS walls (Eqs. 4.7-4.8) normal to the last axis */
     double theta_wall[2]; /* wall temperatures: [0] at index 0, [1] at index n-1 */
     double u_wall[2][3];  /* wall velocities, same order */
@@ -141,10 +146,17 @@ holb_status holb_reduce(holb_sim* s, double out[5]);
 holb_status holb_error_flags(holb_sim* s, uint32_t* flags);
 
 /* Raw population state: size in bytes, and device-to-device copies out of /
- * into the library's current buffer (layout: Q planes of 256-byte aligned
- * pitch, element type per storage, velocity order of holb_lattice_info; the
- * buffer holds the post-collision populations of the last step, so that
- * pulling f^(x) = buf[i][x - c_i] gives the current pre-collision state). */
+ * into the library's current buffer.  Layout: Q planes of 256-byte aligned
+ * pitch (element type per storage, velocity order of holb_lattice_info),
+ * then one 32-bit word per cell holding the cell's frame, binary16 rho_F in
+ * the low half and binary16 theta_F in the high half.  Slot i of cell y holds
+ * the post-collision population f*_i(y) of the last step in the frame of y:
+ * h = f*_i / w_i - rho_F (1 + t_i(u = 0, theta_F)) of Eq. (2.2) in FP32
+ * storage, h - d_i rounded to the 16-bit format otherwise, with
+ * d_i = (f^eq_i(rho0, u0, theta0) - f^eq_i(rho0, 0, theta0)) / w_i; pulling
+ * slot i of y = x - c_i gives the pre-collision population of x.  The format
+ * is the library's own: copy it back only into a simulation of the same
+ * configuration. */
 holb_status holb_state_bytes(holb_sim* s, size_t* bytes);
 holb_status holb_get_state(holb_sim* s, void* dev_dst, size_t bytes);
 holb_status holb_set_state(holb_sim* s, const void* dev_src, size_t bytes);

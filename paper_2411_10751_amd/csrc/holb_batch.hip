@@ -22,7 +22,7 @@ namespace holb {
 struct RunDesc {
     int nx, ny, N;
     unsigned flags;
-    long long off;     // element offset of the run's planes in a population buffer
+    long long off;     // element offset of the run's planes (Q, then frames) in a population buffer
     long long pitch;   // elements per population plane of this run
     long long cell0;   // offset of the run's cells in the theta field
     float omega, kappa, g0, g1, hfac;
@@ -210,7 +210,7 @@ void plan(holb_batch* b, const holb_config* cfgs, int n)
         d.pitch = (long long)align_up((size_t)d.N, 64);
         d.off = (long long)elems;
         d.cell0 = (long long)cells;
-        elems += (size_t)D2Q37::Q * d.pitch;
+        elems += (size_t)(D2Q37::Q + 1) * d.pitch;  // Q planes, then the frame plane
         cells += align_up((size_t)d.N, 64);
         for (int c0 = 0; c0 < d.N; c0 += BATCH_ITEM) b->items.push_back(make_int2(r, c0));
         maxblk = std::max(maxblk, (d.N + 255) / 256);

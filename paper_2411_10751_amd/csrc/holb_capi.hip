@@ -46,7 +46,9 @@ Layout layout_of(const holb_config* c)
     const size_t N = (size_t)c->nx * c->ny * c->nz;
     L.elem = c->storage == HOLB_STORE_F32 ? 4 : 2;
     L.pitch = align_up(N, ALIGN / L.elem);
-    L.pop_bytes = (size_t)Q * L.pitch * L.elem;
+    // Q population planes, then one binary16 pair (rho, theta) per cell: the
+    // frame the cell's populations are stored in
+    L.pop_bytes = (size_t)Q * L.pitch * L.elem + align_up(N * 4);
     size_t off = 0;
     L.pop_off[0] = off; off = align_up(off + L.pop_bytes);
     L.pop_off[1] = off; off = align_up(off + L.pop_bytes);

@@ -27,55 +27,92 @@ __device__ __forceinline__ void cell_coords(const KParams& p, int cell, int& x, 
     z = r / p.ny;
 }
 
-// Pull the Q populations of node (x, y, z).  Along the wall-normal axis of a
-// walled domain, sources outside [0, n) are not read; their bits are returned.
-// Nodes at least 3 cells from every edge take the source of population i at
-// cell - shift_i with a wave-uniform shift, so that each load is a uniform
-// base plus one shared per-lane offset; the others wrap per coordinate.
-// WALLS = false compiles the periodic pull only (no wall bookkeeping).
+// Pull the Q populations of node (x, y, z) into the node's own frame fo (read
+// from the frame plane of fin at the node).  Along the wall-normal axis of a
+// walled domain, sources outside [0, n) are not read; their bits are
+// returned.  Nodes at least 3 cells from every edge take the source of
+// population i at cell - shift_i with a wave-uniform shift, so that each load
+// is a uniform base plus one shared per-lane offset; the others wrap per
+// coordinate.  WALLS = false compiles the periodic pull only.
 template <class L, int ST, bool WALLS>
 __device__ __forceinline__ uint64_t pull_cell(const KParams& p, const typename Codec<ST>::T* __restrict__ fin,
-                                              int x, int y, int z, float (&f)[L::Q])
+                                              int x, int y, int z, float (&f)[L::Q], Frame& fo)
 {
+    using LL = Lat<L>;
+    using T = typename Codec<ST>::T;
+    const uint32_t* __restrict__ fp = frame_plane<ST>(fin, p.pitch, L::Q);
+    const int cell = (z * p.ny + y) * p.nx + x;
     const bool inner = x >= 3 && x < p.nx - 3 && y >= 3 && y < p.ny - 3 &&
                        (L::D == 2 || (z >= 3 && z < p.nz - 3));
+    const bool walls = WALLS && p.walls;
+    // source cell of every population (or -1 where the source lies beyond a
+    // wall): all addresses first, then all loads, then the arithmetic, so
+    // that the loads of a node are in flight together
+    int src[L::Q];
+    uint64_t unk = 0;
     if (inner) {
-        const int cell = (z * p.ny + y) * p.nx + x;
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) src[i] = cell - ((L::cz[i] * p.ny + L::cy[i]) * p.nx + L::cx[i]);
+    } else {
+        int xs[7], ys[7], zs[7];
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+            xs[k] = wrapc(x + k - 3, p.nx);
+            ys[k] = (L::D == 2 && walls) ? y + k - 3 : wrapc(y + k - 3, p.ny);
+            zs[k] = (L::D == 3) ? (walls ? z + k - 3 : wrapc(z + k - 3, p.nz)) : 0;
+        }
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) {
-            const int shift = (L::cz[i] * p.ny + L::cy[i]) * p.nx + L::cx[i];
-            const typename Codec<ST>::T* base = fin + (long long)i * p.pitch - shift;
-            f[i] = Codec<ST>::dec(base[cell], p.dref[i]);
+            const int sx = xs[3 - L::cx[i]], sy = ys[3 - L::cy[i]], sz = zs[3 - L::cz[i]];
+            bool known = true;
+            if (walls) {
+                const int kw = (L::D == 2) ? sy : sz;
+                const int nw = (L::D == 2) ? p.ny : p.nz;
+                known = (kw >= 0 && kw < nw);
+            }
+            src[i] = known ? (sz * p.ny + sy) * p.nx + sx : -1;
+            if (!known) unk |= 1ull << i;
         }
-        return 0;
     }
-    const bool walls = WALLS && p.walls;
-    int xs[7], ys[7], zs[7];
-#pragma unroll
-    for (int k = 0; k < 7; ++k) {
-        xs[k] = wrapc(x + k - 3, p.nx);
-        ys[k] = (L::D == 2 && walls) ? y + k - 3 : wrapc(y + k - 3, p.ny);
-        zs[k] = (L::D == 3) ? (walls ? z + k - 3 : wrapc(z + k - 3, p.nz)) : 0;
-    }
-    uint64_t unk = 0;
+    T raw[L::Q];
+    uint32_t fw[L::Q];
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
-        const int sx = xs[3 - L::cx[i]], sy = ys[3 - L::cy[i]], sz = zs[3 - L::cz[i]];
-        bool known = true;
-        if (walls) {
-            const int kw = (L::D == 2) ? sy : sz;
-            const int nw = (L::D == 2) ? p.ny : p.nz;
-            known = (kw >= 0 && kw < nw);
-        }
-        if (known) {
-            const int idx = (sz * p.ny + sy) * p.nx + sx;
-            f[i] = Codec<ST>::dec(fin[(long long)i * p.pitch + idx], p.dref[i]);
-        } else {
-            f[i] = 0.0f;
-            unk |= 1ull << i;
-        }
+        const int sc = src[i] < 0 ? cell : src[i];  // unknown: any valid slot, value discarded
+        raw[i] = fin[(long long)i * p.pitch + sc];
+        fw[i] = fp[sc];
+    }
+    // keep the scheduler from sinking loads into the arithmetic below: all
+    // 2Q loads of the node are issued before the first one is consumed
+    __builtin_amdgcn_sched_barrier(0);
+    fo = unpack_frame(fw[0]);
+    const FrameRef<L> ref = frame_ref<L>(fo);
+    f[0] = Codec<ST>::dec(raw[0], p.dref[0]);
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) {
+        const float v = Codec<ST>::dec(raw[i], p.dref[i]) + frame_shift<L>(ref, L::shell[i], unpack_frame(fw[i]));
+        f[i] = ((unk >> i) & 1ull) ? 0.0f : v;
     }
     return unk;
+}
+
+// Store the post-collision populations of a node in a new frame fn (written
+// to the frame plane of fout): h_i(fn) = h_i(fo) + R_i(fo) - R_i(fn), one
+// shift per shell.
+template <class L, int ST>
+__device__ __forceinline__ void store_cell(const KParams& p, typename Codec<ST>::T* __restrict__ fout, long long cell,
+                                           float (&f)[L::Q], const Frame& fo, float rho, float thb)
+{
+    const uint32_t packed = pack_frame(rho, thb);
+    frame_plane<ST>(fout, p.pitch, L::Q)[cell] = packed;
+    const Frame fn = unpack_frame(packed);
+    const FrameRef<L> ref = frame_ref<L>(fo);
+    float sh[L::NS];  // R(fo) - R(fn)
+#pragma unroll
+    for (int s = 0; s < L::NS; ++s) sh[s] = -frame_shift<L>(ref, s, fn);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i)
+        fout[(long long)i * p.pitch + cell] = Codec<ST>::enc(f[i] + sh[L::shell[i]], p.dref[i]);
 }
 
 template <class L>
@@ -85,16 +122,17 @@ __device__ __forceinline__ void wall_coord(const KParams& p, int x, int y, int z
     else { kw = z; nw = p.nz; cil = x + p.nx * y; }
 }
 
-// Pull + wall closure + deviation moments (dr = rho - rho0, j, ed = e -
-// rho0 D c0^2; no stencil force yet).  Shared by every pass over the state so
-// that they agree bitwise.  f holds the deviations h_i.  WALLS = false
-// compiles out the wall closure (periodic domains and interior planes).
+// Pull + wall closure + deviation moments in the node's frame fo (dr = rho -
+// rho_F, j, ed = e - rho_F D c0^2 theta_F; no stencil force yet).  Shared by
+// every pass over the state so that they agree bitwise.  f holds the
+// deviations h_i.  WALLS = false compiles out the wall closure (periodic
+// domains and interior planes).
 template <class L, int ST, bool WALLS>
 __device__ __forceinline__ void load_state(const KParams& p, const typename Codec<ST>::T* __restrict__ fin,
                                            const float* __restrict__ tgt_in, int x, int y, int z,
-                                           float (&f)[L::Q], float& dr, float (&j)[3], float& ed)
+                                           float (&f)[L::Q], Frame& fo, float& dr, float (&j)[3], float& ed)
 {
-    uint64_t unk = pull_cell<L, ST, WALLS>(p, fin, x, y, z, f);
+    uint64_t unk = pull_cell<L, ST, WALLS>(p, fin, x, y, z, f, fo);
     if (WALLS && p.walls && unk) {
         int kw, nw, cil;
         wall_coord<L>(p, x, y, z, kw, nw, cil);
@@ -103,7 +141,7 @@ __device__ __forceinline__ void load_state(const KParams& p, const typename Code
 #pragma unroll
         for (int c = 0; c < L::D + 2; ++c) t[c] = tgt_in[((long long)slot * (L::D + 2) + c) * p.nlayer + cil];
         const int wall = kw == 0 ? 0 : (kw == nw - 1 ? 1 : -1);
-        tms_fill<L>(p, f, unk, wall, t);
+        tms_fill<L>(p, fo, f, unk, wall, t);
     }
     moments<L>(f, dr, j, ed);
 }
@@ -180,7 +218,7 @@ __device__ __forceinline__ void write_targets(const KParams& p, float* __restric
 }
 
 template <class L, int ST, int FAM>
-__device__ __forceinline__ void full_macro(const KParams& p, const float* __restrict__ aux_f,
+__device__ __forceinline__ void full_macro(const KParams& p, const Frame& fo, const float* __restrict__ aux_f,
                                            const double* __restrict__ aux_d, int x, int y, int z, float dr,
                                            const float (&j)[3], float ed, Macro& m, float& pc)
 {
@@ -193,7 +231,14 @@ __device__ __forceinline__ void full_macro(const KParams& p, const float* __rest
         for (int a = 0; a < 3; ++a) Fext[a] = (float)Fsc[a];
         pc = ptensor_coef(p, psi_x, Fsc);
     }
-    macro_from_moments<L>(p, dr, j, ed, Fext, m);
+    macro_from_moments<L>(p, fo, dr, j, ed, Fext, m);
+}
+
+// Temperature field value of a node for the gradient stencil: theta minus
+// the global reference theta0, from the frame offset and the deviation.
+__device__ __forceinline__ float theta_field(const KParams& p, const Frame& fo, const Macro& m)
+{
+    return (fo.thb - p.thb_ref) + m.dth;
 }
 
 // One full step of one cell: pull, closure, moments, sources, collision and
@@ -208,10 +253,11 @@ __device__ __forceinline__ void step_cell(const KParams& p, const typename Codec
     int x, y, z;
     cell_coords<L>(p, cell, x, y, z);
     float f[L::Q], dr, j[3], ed;
-    load_state<L, ST, WALLS>(p, fin, tgt_in, x, y, z, f, dr, j, ed);
+    Frame fo;
+    load_state<L, ST, WALLS>(p, fin, tgt_in, x, y, z, f, fo, dr, j, ed);
     Macro m;
     float pc;
-    full_macro<L, ST, FAM>(p, aux_f, aux_d, x, y, z, dr, j, ed, m, pc);
+    full_macro<L, ST, FAM>(p, fo, aux_f, aux_d, x, y, z, dr, j, ed, m, pc);
     if (WALLS && p.walls) write_targets<L>(p, tgt_out, x, y, z, m);
     float gT[3] = {0.f, 0.f, 0.f};
     float hc = 0.0f;
@@ -219,10 +265,8 @@ __device__ __forceinline__ void step_cell(const KParams& p, const typename Codec
         grad_theta<L>(p, aux_f, x, y, z, gT);
         hc = p.hfac * m.rho * m.theta;
     }
-    collide<L>(p, f, m, hc, gT, pc);
-#pragma unroll
-    for (int i = 0; i < L::Q; ++i)
-        fout[(long long)i * p.pitch + cell] = Codec<ST>::enc(f[i], p.dref[i]);
+    collide<L>(p, fo, f, m, hc, gT, pc);
+    store_cell<L, ST>(p, fout, cell, f, fo, m.rho, m.thb);
 }
 
 // Field pass of one cell: theta (thermal family) or psi (pressure-tensor
@@ -235,21 +279,34 @@ __device__ __forceinline__ void aux_cell(const KParams& p, const typename Codec<
     int x, y, z;
     cell_coords<L>(p, cell, x, y, z);
     float f[L::Q], dr, j[3], ed;
-    load_state<L, ST, WALLS>(p, fin, tgt_in, x, y, z, f, dr, j, ed);
+    Frame fo;
+    load_state<L, ST, WALLS>(p, fin, tgt_in, x, y, z, f, fo, dr, j, ed);
     if (FAM == FAM_PTENSOR) {
         bool bad = false;
-        aux_d[cell] = psi_vdw(p, (double)p.rho_ref + (double)dr, L::c0sq, bad);
+        aux_d[cell] = psi_vdw(p, (double)fo.rho + (double)dr, L::c0sq, bad);
         if (bad) raise_err(p, HOLB_ERR_EOS_BIT);
     } else {
         const float z3[3] = {0.f, 0.f, 0.f};
         Macro m;
-        macro_from_moments<L>(p, dr, j, ed, z3, m);
-        aux_f[cell] = m.dth;  // theta - theta0: its differences are grad theta
+        macro_from_moments<L>(p, fo, dr, j, ed, z3, m);
+        aux_f[cell] = theta_field(p, fo, m);
     }
 }
 
+// Initial frame of one cell (written before the populations, which are
+// stored in the frames of the cells they are pulled from).
+template <class L, int ST>
+__device__ __forceinline__ void init_frame_cell(const KParams& p, const float* __restrict__ rho,
+                                                const float* __restrict__ theta, typename Codec<ST>::T* __restrict__ fout,
+                                                int cell)
+{
+    const float thb = (p.flags & KF_ISO) ? 0.0f : theta[cell] - 1.0f;
+    frame_plane<ST>(fout, p.pitch, L::Q)[cell] = pack_frame(rho[cell], thb);
+}
+
 // Initial state of one cell: f^0_i(x) = f^eq_i(rho, u, theta)(x), written to
-// the slot x - c_i that the first pull of node x reads.
+// the slot x - c_i that the first pull of node x reads, in the frame of that
+// slot's cell.
 template <class L, int ST>
 __device__ __forceinline__ void init_cell(const KParams& p, const float* __restrict__ rho,
                                           const float* __restrict__ u, const float* __restrict__ theta,
@@ -268,6 +325,9 @@ __device__ __forceinline__ void init_cell(const KParams& p, const float* __restr
     if (!(m.rho > 0.0f) || !(m.rho < 3.0e38f)) raise_err(p, HOLB_ERR_DENSITY_BIT);
     if (!(m.theta > 0.0f) || !(m.theta < 3.0e38f)) raise_err(p, HOLB_ERR_THETA_BIT);
     if (p.walls) write_targets<L>(p, tgt, x, y, z, m);
+    const uint32_t* fp = frame_plane<ST>(fout, p.pitch, L::Q);
+    const Frame fo = unpack_frame(fp[cell]);
+    const FrameRef<L> ref = frame_ref<L>(fo);
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
         int dx = wrapc(x - L::cx[i], p.nx);
@@ -285,8 +345,12 @@ __device__ __forceinline__ void init_cell(const KParams& p, const float* __restr
             else dz = wrapc(dz, p.nz);
         }
         if (!inside) continue;
-        const float fe = feq_dev<L>(p, i, m.rho, m.u, m.thb);
-        fout[(long long)i * p.pitch + (dz * p.ny + dy) * p.nx + dx] = Codec<ST>::enc(fe, p.dref[i]);
+        const int slot = (dz * p.ny + dy) * p.nx + dx;
+        const Frame fs = unpack_frame(fp[slot]);
+        // in the node's own frame, then moved into the slot cell's frame
+        const float fe = feq_dev<L>(fo, i, m.rho, m.u, m.thb);
+        const float h = fe - frame_shift<L>(ref, L::shell[i], fs);
+        fout[(long long)i * p.pitch + slot] = Codec<ST>::enc(h, p.dref[i]);
     }
 }
 

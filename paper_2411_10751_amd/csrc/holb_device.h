@@ -1,12 +1,16 @@
 // Device-side building blocks of the fused high-order LBM step (gfx950).
 //
-// Populations are handled in deviation form, h_i = f_i / w_i - r_i, with
-// r_i = rho0 (1 + t0_i) the equilibrium bracket of a reference state at rest,
-// f^eq_i(rho0, 0, theta0) / w_i, and t0_i = t_i(u = 0, theta0) of Eq. (2.2).
-// In exact arithmetic this is the same scheme; in FP32 the large constant part
-// cancels exactly instead of being rounded in every collision, which keeps
-// the round-off of density, velocity and temperature at the level of their
-// deviations from the reference.
+// Populations are handled in deviation form relative to a per-cell frame: a
+// node whose frame is (rho_F, theta_F) holds h_i = f_i / w_i - R_i(F), with
+// R_i(F) = rho_F (1 + t_i(u = 0, theta_F)) the equilibrium bracket of Eq.
+// (2.2) at rest in that frame.  Every node stores its frame (rho and theta
+// rounded to binary16) beside its populations; a node that pulls population
+// i from x - c_i moves it from the source's frame into its own by adding
+// R_i(source) - R_i(own), formed as a difference of neighbouring values.  In
+// exact arithmetic this is the same scheme; in FP32 and in 16-bit storage the
+// values handled stay at the size of the local non-equilibrium and gradient
+// parts instead of the variation of density and temperature across the
+// domain, so their round-off is correspondingly smaller.
 //
 // Every kernel variant (generic one-cell-per-thread, plane-marching, batched)
 // calls the same inline functions below, and the library is compiled with
@@ -45,9 +49,8 @@ struct Lat : L {
 
 // ------------------------------------------------------------------ codec
 // FP32 storage holds h_i.  16-bit storage holds q_i = h_i - d_i rounded to
-// nearest-even, where d_i = f^eq_i(rho0, u0, theta0) / w_i - rho0 centres the
-// stored values on the reference state; this is the deviation
-// (f_i - f^eq_i(reference)) / w_i.
+// nearest-even, where d_i = (f^eq_i(rho0, u0, theta0) - f^eq_i(rho0, 0,
+// theta0)) / w_i removes the bracket of a uniform background velocity u0.
 
 template <int ST>
 struct Codec;
@@ -95,6 +98,43 @@ __device__ __forceinline__ void raise_err(const KParams& p, unsigned bit)
     if (p.err) atomicOr(p.err, bit);
 }
 
+// ------------------------------------------------------------- frames
+// A node's frame: rho_F and thb_F = theta_F - 1, decoded from the packed
+// binary16 pair (rho, theta - 1) stored per cell.
+
+struct Frame {
+    float rho, thb;
+};
+
+__device__ __forceinline__ uint32_t pack_frame(float rho, float thb)
+{
+    const uint16_t r = __builtin_bit_cast(uint16_t, (_Float16)rho);
+    const uint16_t t = __builtin_bit_cast(uint16_t, (_Float16)thb);
+    return (uint32_t)r | ((uint32_t)t << 16);
+}
+
+__device__ __forceinline__ Frame unpack_frame(uint32_t v)
+{
+    Frame F;
+    F.rho = (float)__builtin_bit_cast(_Float16, (uint16_t)(v & 0xffffu));
+    F.thb = (float)__builtin_bit_cast(_Float16, (uint16_t)(v >> 16));
+    return F;
+}
+
+// Per-cell frame plane stored after the Q population planes of a buffer.
+template <int ST>
+__device__ __forceinline__ const uint32_t* frame_plane(const void* pop, long long pitch, int Q)
+{
+    using T = typename Codec<ST>::T;
+    return (const uint32_t*)((const T*)pop + (long long)Q * pitch);
+}
+template <int ST>
+__device__ __forceinline__ uint32_t* frame_plane(void* pop, long long pitch, int Q)
+{
+    using T = typename Codec<ST>::T;
+    return (uint32_t*)((T*)pop + (long long)Q * pitch);
+}
+
 // ----------------------------------------------------- kinetic algebra
 // Lattice units outside; a = c.u / c0^2, uu = |u|^2 / c0^2, xx = |c|^2 / c0^2
 // and thb = theta - 1 are the Hermite-scaled invariants of Eq. (2.2) / Table 2.
@@ -128,21 +168,70 @@ __device__ __forceinline__ float ref_t0(float xx, float thb0)
     return thb0 * fmaf(thb0, q2, 0.5f * (xx - D));
 }
 
-// f^eq_i / w_i - r_i (used by the wall closure and the initialisation; the
-// collision evaluates the equilibrium per +/-c pair instead).
+// Frame shifts R_i(S) - R_i(O), R_i(F) = rho_F (1 + t0(thb_F)).  With
+// a = rho_S - rho_O, b = thb_S - thb_O, X = xx - D and Y/8 = q2 the theta^2
+// coefficient of t0, the difference of two close brackets is
+//   R_i(S) - R_i(O) = a T_O + rho_S b (K_O + b q2),
+//   T_O = 1 + t0(thb_O),  K_O = X/2 + 2 thb_O q2,
+// formed without either bracket.  FrameRef holds T_O and K_O per shell.
 template <class L>
-__device__ __forceinline__ float feq_dev(const KParams& p, int i, float rho, const float (&u)[3], float thb)
+struct FrameRef {
+    float rho, thb;
+    float T[L::NS], K[L::NS];
+};
+
+template <class L>
+__device__ __forceinline__ float shell_q2(int s)
+{
+    constexpr float D = (float)L::D;
+    const float xx = (float)L::shell_c2[s] * Lat<L>::ic0sq;
+    return 0.125f * (xx * xx - 2.0f * (D + 2.0f) * xx + D * (D + 2.0f));
+}
+
+template <class L>
+__device__ __forceinline__ float shell_hx(int s)
+{
+    return 0.5f * ((float)L::shell_c2[s] * Lat<L>::ic0sq - (float)L::D);
+}
+
+template <class L>
+__device__ __forceinline__ FrameRef<L> frame_ref(const Frame& O)
+{
+    FrameRef<L> r;
+    r.rho = O.rho;
+    r.thb = O.thb;
+#pragma unroll
+    for (int s = 0; s < L::NS; ++s) {
+        const float q2 = shell_q2<L>(s), hx = shell_hx<L>(s);
+        r.T[s] = 1.0f + O.thb * fmaf(O.thb, q2, hx);
+        r.K[s] = fmaf(2.0f * O.thb, q2, hx);
+    }
+    return r;
+}
+
+template <class L>
+__device__ __forceinline__ float frame_shift(const FrameRef<L>& O, int s, const Frame& S)
+{
+    const float a = S.rho - O.rho, b = S.thb - O.thb;
+    const float k = fmaf(b, shell_q2<L>(s), O.K[s]);
+    return fmaf(S.rho * b, k, a * O.T[s]);
+}
+
+// f^eq_i / w_i - R_i(F) (used by the wall closure and the initialisation;
+// the collision evaluates the equilibrium per +/-c pair instead).
+template <class L>
+__device__ __forceinline__ float feq_dev(const Frame& F, int i, float rho, const float (&u)[3], float thb)
 {
     using LL = Lat<L>;
-    const float t0 = ref_t0<L>((float)LL::c2(i) * LL::ic0sq, p.thb_ref);
-    return (rho - p.rho_ref) * (1.0f + t0) + rho * (feq_t<L>(i, u, thb) - t0);
+    const float t0 = ref_t0<L>((float)LL::c2(i) * LL::ic0sq, F.thb);
+    return (rho - F.rho) * (1.0f + t0) + rho * (feq_t<L>(i, u, thb) - t0);
 }
 
 // Macroscopic state of a node from the shifted moments of Eq. (4.5):
 // rho = sum f, rho u = sum c f + F/2, and rho D c0^2 theta = sum |c|^2 f -
-// rho |u|^2 + u.F (tr G_2 = 2 u.F).  dr = rho - rho0, dth = theta - theta0,
-// thb = theta - 1; j = sum c f and ed = sum |c|^2 f - rho0 D c0^2 theta0 are
-// kept for the conservation check.
+// rho |u|^2 + u.F (tr G_2 = 2 u.F).  In the node's frame F: dr = rho - rho_F,
+// dth = theta - theta_F, thb = theta - 1; j = sum c f and ed = sum |c|^2 f -
+// rho_F D c0^2 theta_F are kept for the conservation check.
 struct Macro {
     float rho, dr, u[3], dth, thb, theta, F[3];
     float j[3], ed;
@@ -172,11 +261,11 @@ __device__ __forceinline__ void moments(const float (&h)[L::Q], float& dr, float
 }
 
 template <class L, bool RAISE = true>
-__device__ __forceinline__ void macro_from_moments(const KParams& p, float dr, const float (&j)[3], float ed,
-                                                   const float (&Fext)[3], Macro& m)
+__device__ __forceinline__ void macro_from_moments(const KParams& p, const Frame& fr, float dr, const float (&j)[3],
+                                                   float ed, const float (&Fext)[3], Macro& m)
 {
     using LL = Lat<L>;
-    const float rho = p.rho_ref + dr;
+    const float rho = fr.rho + dr;
     m.rho = rho;
     m.dr = dr;
     m.ed = ed;
@@ -197,10 +286,10 @@ __device__ __forceinline__ void macro_from_moments(const KParams& p, float dr, c
     } else {
         const float uu = m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2];
         const float uF = m.u[0] * m.F[0] + m.u[1] * m.F[1] + m.u[2] * m.F[2];
-        // theta - theta0 = (e - rho |u|^2 + u.F - rho D c0^2 theta0) / (rho D c0^2)
-        const float th0 = 1.0f + p.thb_ref;
+        // theta - theta_F = (e - rho |u|^2 + u.F - rho D c0^2 theta_F) / (rho D c0^2)
+        const float th0 = 1.0f + fr.thb;
         m.dth = ((ed - dr * (LL::DC * th0)) - rho * uu + uF) / (rho * LL::DC);
-        m.thb = p.thb_ref + m.dth;
+        m.thb = fr.thb + m.dth;
         m.theta = th0 + m.dth;
     }
     if (RAISE) {
@@ -216,8 +305,8 @@ __device__ __forceinline__ void macro_from_moments(const KParams& p, float dr, c
 // theta) of this node; wall = 0/1 for a wall node (first/last layer), -1 for
 // a fluid node, whose target is its own previous-step state.
 template <class L>
-__device__ __forceinline__ void tms_fill(const KParams& p, float (&h)[L::Q], uint64_t unk, int wall,
-                                         const float* tgt)
+__device__ __forceinline__ void tms_fill(const KParams& p, const Frame& fr, float (&h)[L::Q], uint64_t unk,
+                                         int wall, const float* tgt)
 {
     using LL = Lat<L>;
     constexpr int D = L::D;
@@ -237,12 +326,12 @@ __device__ __forceinline__ void tms_fill(const KParams& p, float (&h)[L::Q], uin
     const float tbt = tt - 1.0f;
 #pragma unroll
     for (int i = 0; i < L::Q; ++i)
-        if ((unk >> i) & 1ull) h[i] = feq_dev<L>(p, i, rt, ut, tbt);  // target equilibrium, for now
+        if ((unk >> i) & 1ull) h[i] = feq_dev<L>(fr, i, rt, ut, tbt);  // target equilibrium, for now
     float drl, jl[3], edl;
     moments<L>(h, drl, jl, edl);
     const float zero3[3] = {0.f, 0.f, 0.f};
     Macro loc;
-    macro_from_moments<L, false>(p, drl, jl, edl, zero3, loc);
+    macro_from_moments<L, false>(p, fr, drl, jl, edl, zero3, loc);
     // the difference of the two equilibria is small next to each of them:
     // form it in FP64 (wall layers only)
 #pragma unroll
@@ -287,15 +376,15 @@ __device__ __forceinline__ void conserve(const KParams& p, float (&h)[L::Q], con
     }
 }
 
-// Eq. (4.4) collision, h* = (1 - om) h + om (f^eq / w_i - r_i) + (1 - 1/(2 tau_hat)) S / w_i,
+// Eq. (4.4) collision, h* = (1 - om) h + om (f^eq / w_i - R_i(F)) + (1 - 1/(2 tau_hat)) S / w_i,
 // with f^eq of Eq. (2.2) and S = F (Eq. 3.3) + H (Eq. 3.7) + P (Eq. 3.12),
 // evaluated once per +/-c pair from its even and odd parts.
 //   hc    = (1 - 1/Pr) rho theta / 2   (0 without the thermal source)
 //   gT    = grad theta per lattice spacing
 //   pc    = -(k / (2 D tau)) |F^SC|^2 / (c0^2 G psi^2)   (0 without it)
 template <class L>
-__device__ __forceinline__ void collide(const KParams& p, float (&h)[L::Q], const Macro& m, float hc,
-                                        const float (&gT)[3], float pc)
+__device__ __forceinline__ void collide(const KParams& p, const Frame& fr, float (&h)[L::Q], const Macro& m,
+                                        float hc, const float (&gT)[3], float pc)
 {
     using LL = Lat<L>;
     constexpr int D = L::D;
@@ -303,7 +392,7 @@ __device__ __forceinline__ void collide(const KParams& p, float (&h)[L::Q], cons
     const float ic = LL::ic0sq;
     const float uu = (m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2]) * ic;
     const float UF = (m.u[0] * m.F[0] + m.u[1] * m.F[1] + m.u[2] * m.F[2]) * ic;
-    const float thb = m.thb, dth = m.dth, thb0 = p.thb_ref;
+    const float thb = m.thb, dth = m.dth, thb0 = fr.thb;
     const float om = p.omega, ka = p.kappa, om1 = 1.0f - p.omega;
     const float orho = om * m.rho;
     const float odr = om * m.dr;
@@ -312,8 +401,8 @@ __device__ __forceinline__ void collide(const KParams& p, float (&h)[L::Q], cons
 
     // per-shell coefficients of the even (dK0, K2) and odd (K1) parts of the
     // equilibrium bracket and of the force source (M1); HS, PS of H and P.
-    // dK0 = K0 - (1 + t0) is the even bracket relative to the reference
-    // (thb^2 - thb0^2 = dth (thb + thb0)); R0 = 1 + t0.
+    // dK0 = K0 - (1 + t0) is the even bracket relative to the frame
+    // (thb^2 - thb0^2 = dth (thb + thb0)); R0 = 1 + t0 of the frame.
     float dK0[L::NS], R0[L::NS], K1[L::NS], K2[L::NS], M1[L::NS], HS[L::NS], PS[L::NS];
     const float muu = -0.5f * uu;
 #pragma unroll

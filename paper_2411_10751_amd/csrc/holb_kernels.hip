@@ -1,7 +1,8 @@
 // gfx950 kernels of the high-order lattice Boltzmann step and their launchers.
 //
 // Data layout: populations are structure-of-arrays, Q planes of `pitch`
-// elements (256-byte aligned), cell = x + nx * (y + ny * z).  The state buffer
+// elements (256-byte aligned), cell = x + nx * (y + ny * z), followed by the
+// plane of per-cell frames (binary16 pairs rho, theta).  The state buffer
 // holds the post-collision populations of the last step; a step pulls
 // f^_i(x) = buf[i][x - c_i] (streaming, left side of Eq. 4.4), applies the wall
 // closure, forms the shifted moments (Eq. 4.5), the sources and the collision,
@@ -23,6 +24,15 @@ namespace holb {
 constexpr int GEN_BLOCK = 256;
 
 // --------------------------------------------------------------- kernels
+
+template <class L, int ST>
+__global__ void __launch_bounds__(GEN_BLOCK)
+k_init_frame(const KParams p, const float* __restrict__ rho, const float* __restrict__ theta,
+             typename Codec<ST>::T* __restrict__ fout)
+{
+    const int cell = xcd_block() * GEN_BLOCK + threadIdx.x;
+    if (cell < p.N) init_frame_cell<L, ST>(p, rho, theta, fout, cell);
+}
 
 template <class L, int ST>
 __global__ void __launch_bounds__(GEN_BLOCK)
@@ -78,10 +88,11 @@ k_fields(const KParams p, const typename Codec<ST>::T* __restrict__ fin, const f
     int x, y, z;
     cell_coords<L>(p, cell, x, y, z);
     float f[L::Q], dr, j[3], ed;
-    load_state<L, ST, WALLS>(p, fin, tgt_in, x, y, z, f, dr, j, ed);
+    Frame fo;
+    load_state<L, ST, WALLS>(p, fin, tgt_in, x, y, z, f, fo, dr, j, ed);
     Macro m;
     float pc;
-    full_macro<L, ST, FAM>(p, aux_f, aux_d, x, y, z, dr, j, ed, m, pc);
+    full_macro<L, ST, FAM>(p, fo, aux_f, aux_d, x, y, z, dr, j, ed, m, pc);
     if (rho_out) rho_out[cell] = m.rho;
     if (u_out) {
 #pragma unroll
@@ -111,18 +122,19 @@ k_reduce(const KParams p, const typename Codec<ST>::T* __restrict__ fin, const f
         int x, y, z;
         cell_coords<L>(p, cell, x, y, z);
         float f[L::Q], dr, j[3], ed;
-        load_state<L, ST, WALLS>(p, fin, tgt_in, x, y, z, f, dr, j, ed);
+        Frame fo;
+        load_state<L, ST, WALLS>(p, fin, tgt_in, x, y, z, f, fo, dr, j, ed);
         Macro m;
         float pc;
-        full_macro<L, ST, FAM>(p, aux_f, aux_d, x, y, z, dr, j, ed, m, pc);
-        // mass from the deviation moment, in FP64
-        const double r = (double)p.rho_ref + (double)m.dr;
+        full_macro<L, ST, FAM>(p, fo, aux_f, aux_d, x, y, z, dr, j, ed, m, pc);
+        // mass from the frame and the deviation moment, in FP64
+        const double r = (double)fo.rho + (double)m.dr;
         v[0] = r;
         v[1] = r * (double)m.u[0];
         v[2] = r * (double)m.u[1];
         v[3] = r * (double)m.u[2];
         const double uu = (double)m.u[0] * m.u[0] + (double)m.u[1] * m.u[1] + (double)m.u[2] * m.u[2];
-        v[4] = 0.5 * (r * uu + r * (L::D * L::c0sq) * ((1.0 + (double)p.thb_ref) + (double)m.dth));
+        v[4] = 0.5 * (r * uu + r * (L::D * L::c0sq) * ((1.0 + (double)fo.thb) + (double)m.dth));
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
@@ -171,6 +183,10 @@ struct Launch {
 
     static hipError_t init(const LaunchCtx& c, const float* rho, const float* u, const float* th)
     {
+        hipLaunchKernelGGL((k_init_frame<L, ST>), dim3(nblocks_for(c.kp.N)), dim3(GEN_BLOCK), 0, c.stream, c.kp,
+                           rho, th, (T*)c.pop_out);
+        hipError_t r = hipGetLastError();
+        if (r != hipSuccess) return r;
         hipLaunchKernelGGL((k_init<L, ST>), dim3(nblocks_for(c.kp.N)), dim3(GEN_BLOCK), 0, c.stream, c.kp, rho, u,
                            th, (T*)c.pop_out, (float*)c.tgt_out);
         return hipGetLastError();

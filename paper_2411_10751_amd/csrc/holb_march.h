@@ -66,28 +66,28 @@ __device__ __forceinline__ MarchItem march_item(const KParams& p, int ntx, int n
 template <class L, int ST>
 __device__ __forceinline__ float march_theta(const KParams& p, const typename Codec<ST>::T* __restrict__ fin,
                                              const float* __restrict__ aux_f, int x, int y, int pz, int mlo,
-                                             int mhi, int nm, float (&f)[L::Q])
+                                             int mhi, int nm, float (&f)[L::Q], Frame& fo)
 {
     constexpr bool D3 = L::D == 3;
     if (p.walls && (pz < mlo || pz >= mhi))
         return aux_f[D3 ? ((long long)pz * p.ny + y) * p.nx + x : (long long)pz * p.nx + x];
     const int zz = wrapc(pz, nm);
     float dr, j[3], ed;
-    if (D3) load_state<L, ST, false>(p, fin, nullptr, x, y, zz, f, dr, j, ed);
-    else load_state<L, ST, false>(p, fin, nullptr, x, zz, 0, f, dr, j, ed);
+    if (D3) load_state<L, ST, false>(p, fin, nullptr, x, y, zz, f, fo, dr, j, ed);
+    else load_state<L, ST, false>(p, fin, nullptr, x, zz, 0, f, fo, dr, j, ed);
     const float z3[3] = {0.f, 0.f, 0.f};
     Macro mq;
     // flags are raised once, at the collision of the plane
-    macro_from_moments<L, false>(p, dr, j, ed, z3, mq);
-    return mq.dth;
+    macro_from_moments<L, false>(p, fo, dr, j, ed, z3, mq);
+    return theta_field(p, fo, mq);
 }
 
-// Collision of plane q of the column from its pulled populations f and the
-// theta ring; writes the post-collision populations.
+// Collision of plane q of the column from its pulled populations f (in frame
+// fo) and the theta ring; writes the post-collision populations.
 template <class L, int ST, int TY, int TX>
 __device__ __forceinline__ void march_collide(const KParams& p, typename Codec<ST>::T* __restrict__ fout,
                                               const float (&th)[4][TY][TX], int tx, int ty, int x, int y, int q,
-                                              int nm, float (&f)[L::Q])
+                                              int nm, float (&f)[L::Q], const Frame& fo)
 {
     constexpr bool D3 = L::D == 3;
     const int qq = wrapc(q, nm);
@@ -95,7 +95,7 @@ __device__ __forceinline__ void march_collide(const KParams& p, typename Codec<S
     moments<L>(f, dr, j, ed);
     const float z3[3] = {0.f, 0.f, 0.f};
     Macro m;
-    macro_from_moments<L>(p, dr, j, ed, z3, m);
+    macro_from_moments<L>(p, fo, dr, j, ed, z3, m);
     float gT[3];
     gT[0] = 0.5f * (th[q & 3][ty][tx + 1] - th[q & 3][ty][tx - 1]);
     const float gm = 0.5f * (th[(q + 1) & 3][ty][tx] - th[(q - 1) & 3][ty][tx]);
@@ -106,10 +106,9 @@ __device__ __forceinline__ void march_collide(const KParams& p, typename Codec<S
         gT[1] = gm;
         gT[2] = 0.0f;
     }
-    collide<L>(p, f, m, p.hfac * m.rho * m.theta, gT, 0.0f);
+    collide<L>(p, fo, f, m, p.hfac * m.rho * m.theta, gT, 0.0f);
     const long long cell = D3 ? ((long long)qq * p.ny + y) * p.nx + x : (long long)qq * p.nx + x;
-#pragma unroll
-    for (int i = 0; i < L::Q; ++i) fout[(long long)i * p.pitch + cell] = Codec<ST>::enc(f[i], p.dref[i]);
+    store_cell<L, ST>(p, fout, cell, f, fo, m.rho, m.thb);
 }
 
 // Planes [mlo, mhi) are collided; mlo = 0, mhi = nm for a periodic domain.
@@ -129,18 +128,21 @@ k_march(const KParams p, const typename Codec<ST>::T* __restrict__ fin, typename
     const MarchItem it = march_item<L, S>(p, ntx, nty, mlo, chunk, mhi);
 
     float cur[L::Q], nxt[L::Q];
+    Frame fcur = {0.f, 0.f}, fnxt = {0.f, 0.f};
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) cur[i] = 0.f;
+    for (int i = 0; i < L::Q; ++i) cur[i] = nxt[i] = 0.f;
 
     for (int pz = it.z0 - 1; pz <= it.z1; ++pz) {
         // 1. pull plane pz, its theta into the LDS ring
-        th[pz & 3][ty][tx] = march_theta<L, ST>(p, fin, aux_f, it.x, it.y, pz, mlo, mhi, nm, nxt);
+        th[pz & 3][ty][tx] = march_theta<L, ST>(p, fin, aux_f, it.x, it.y, pz, mlo, mhi, nm, nxt, fnxt);
         __syncthreads();
         // 2. collide plane q = pz - 1, pulled at the previous iteration
         const int q = pz - 1;
-        if (q >= it.z0 && it.interior) march_collide<L, ST, TY, TX>(p, fout, th, tx, ty, it.x, it.y, q, nm, cur);
+        if (q >= it.z0 && it.interior)
+            march_collide<L, ST, TY, TX>(p, fout, th, tx, ty, it.x, it.y, q, nm, cur, fcur);
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) cur[i] = nxt[i];
+        fcur = fnxt;
     }
 }
 
@@ -166,16 +168,18 @@ k_march2(const KParams p, const typename Codec<ST>::T* __restrict__ fin, typenam
     for (int pz = it.z0 - 1; pz <= it.z1; ++pz) {
         {
             float f[L::Q];
-            th[pz & 3][ty][tx] = march_theta<L, ST>(p, fin, aux_f, it.x, it.y, pz, mlo, mhi, nm, f);
+            Frame fo;
+            th[pz & 3][ty][tx] = march_theta<L, ST>(p, fin, aux_f, it.x, it.y, pz, mlo, mhi, nm, f, fo);
         }
         __syncthreads();
         const int q = pz - 1;
         if (q >= it.z0 && it.interior) {
             const int qq = wrapc(q, nm);
             float f[L::Q], dr, j[3], ed;
-            if (D3) load_state<L, ST, false>(p, fin, nullptr, it.x, it.y, qq, f, dr, j, ed);
-            else load_state<L, ST, false>(p, fin, nullptr, it.x, qq, 0, f, dr, j, ed);
-            march_collide<L, ST, TY, TX>(p, fout, th, tx, ty, it.x, it.y, q, nm, f);
+            Frame fo;
+            if (D3) load_state<L, ST, false>(p, fin, nullptr, it.x, it.y, qq, f, fo, dr, j, ed);
+            else load_state<L, ST, false>(p, fin, nullptr, it.x, qq, 0, f, fo, dr, j, ed);
+            march_collide<L, ST, TY, TX>(p, fout, th, tx, ty, it.x, it.y, q, nm, f, fo);
         }
     }
 }

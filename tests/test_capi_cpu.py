@@ -113,7 +113,7 @@ def test_create_is_host_only_and_checks_workspace():
     assert holb.holb_set_variant(h, 10 ** 6) == holb.EUNSUPPORTED
     sb = ctypes.c_size_t()
     assert holb.holb_state_bytes(h, ctypes.byref(sb)) == holb.OK
-    assert sb.value == 37 * 1024 * 4
+    assert sb.value == 37 * 1024 * 4 + 1024 * 4  # Q planes + one frame (2 x binary16) per cell
     assert holb.holb_get_state(h, ctypes.c_void_p(fake), sb.value - 4) == holb.ESIZE
     assert holb.holb_destroy(h) == holb.OK
 

@@ -106,6 +106,7 @@ def main():
     ap.add_argument("--storage", default="f32", choices=list(STORAGE))
     ap.add_argument("--variant", type=int, default=-1, help="-1: autotune")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sweep", action="store_true", help="time every kernel variant (to stderr) before the run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, stream 1 GiB in and 1 GiB out three times (elementwise "
                          "negation of 2^28 float32: the reference dispatch that scales profiler byte counters)")
@@ -128,6 +129,21 @@ def main():
     torch.cuda.set_device(0)
     sim = holb.Sim(cfg)
     sim.init(w["rho"], w["u"], w["theta"])
+    if args.sweep:
+        for v in range(sim.num_variants()):
+            try:
+                sim.set_variant(v)
+            except Exception:
+                continue
+            sim.step(3)
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            sim.step(10)
+            b.record()
+            torch.cuda.synchronize()
+            print("variant %d: %.4f ms/step" % (v, a.elapsed_time(b) / 10), file=sys.stderr, flush=True)
+        sim.init(w["rho"], w["u"], w["theta"])
     if args.variant >= 0:
         sim.set_variant(args.variant)
         variant = args.variant

@@ -116,7 +116,7 @@ holb_status holb_workspace_size(const holb_config* cfg, size_t* bytes);
 /* Validate cfg and bind a caller-owned device workspace (256-byte aligned,
  * at least holb_workspace_size bytes) and stream.  Pure host call: launches
  * nothing.  Errors: HOLB_EINVAL (values, tau_hat <= 0.5, dims), HOLB_ESIZE
- * (workspace), HOLB_EUNSUPPORTED (e.g. thermal source with isothermal=1,
+ * (workspace, or more than 2^29 cells), HOLB_EUNSUPPORTED (e.g. thermal source with isothermal=1,
  * pressure tensor without isothermal=1 or with walls). */
 holb_status holb_create(const holb_config* cfg, void* dev_workspace, size_t bytes, void* hip_stream,
                         holb_sim** out);

@@ -27,6 +27,7 @@ struct RunDesc {
     long long cell0;   // offset of the run's cells in the theta field
     float omega, kappa, g0, g1, hfac;
     float rho_ref, thb_ref;
+    FastDiv div_nx, div_ny;
     int pad;
 };
 
@@ -39,6 +40,9 @@ __device__ __forceinline__ KParams run_params(const RunDesc& r, unsigned* err)
     p.walls = 0;
     p.N = r.N;
     p.nlayer = r.nx;
+    p.div_nx = r.div_nx;
+    p.div_ny = r.div_ny;
+    p.div_layer = r.div_nx;
     p.pitch = r.pitch;
     p.flags = r.flags;
     p.omega = r.omega; p.kappa = r.kappa;
@@ -202,6 +206,8 @@ void plan(holb_batch* b, const holb_config* cfgs, int n)
         RunDesc& d = b->runs[r];
         memset(&d, 0, sizeof d);
         d.nx = c.nx; d.ny = c.ny; d.N = c.nx * c.ny;
+        d.div_nx = make_fastdiv((unsigned)c.nx);
+        d.div_ny = make_fastdiv((unsigned)c.ny);
         const KParams p = params_of(&c);
         d.flags = p.flags;
         d.omega = p.omega; d.kappa = p.kappa; d.g0 = p.g[0]; d.g1 = p.g[1]; d.hfac = p.hfac;

@@ -21,10 +21,11 @@ __device__ __forceinline__ int xcd_block()
 template <class L>
 __device__ __forceinline__ void cell_coords(const KParams& p, int cell, int& x, int& y, int& z)
 {
-    x = cell % p.nx;
-    int r = cell / p.nx;
-    y = r % p.ny;
-    z = r / p.ny;
+    const unsigned r = fastdiv((unsigned)cell, p.div_nx);
+    x = cell - (int)r * p.nx;
+    const unsigned q = fastdiv(r, p.div_ny);
+    y = (int)r - (int)q * p.ny;
+    z = (int)q;
 }
 
 // Pull the Q populations of node (x, y, z) into the node's own frame fo (read
@@ -34,26 +35,53 @@ __device__ __forceinline__ void cell_coords(const KParams& p, int cell, int& x, 
 // population i at cell - shift_i with a wave-uniform shift, so that each load
 // is a uniform base plus one shared per-lane offset; the others wrap per
 // coordinate.  WALLS = false compiles the periodic pull only.
+// Load at a 32-bit byte offset from a base pointer (a wave-uniform base
+// lets the load take the scalar-base + lane-offset addressing form).
+template <class T>
+__device__ __forceinline__ T load_at(const T* __restrict__ base, unsigned byte_off)
+{
+    return *(const T*)((const char*)base + byte_off);
+}
+
 template <class L, int ST, bool WALLS>
 __device__ __forceinline__ uint64_t pull_cell(const KParams& p, const typename Codec<ST>::T* __restrict__ fin,
                                               int x, int y, int z, float (&f)[L::Q], Frame& fo)
 {
-    using LL = Lat<L>;
     using T = typename Codec<ST>::T;
     const uint32_t* __restrict__ fp = frame_plane<ST>(fin, p.pitch, L::Q);
     const int cell = (z * p.ny + y) * p.nx + x;
-    const bool inner = x >= 3 && x < p.nx - 3 && y >= 3 && y < p.ny - 3 &&
-                       (L::D == 2 || (z >= 3 && z < p.nz - 3));
-    const bool walls = WALLS && p.walls;
-    // source cell of every population (or -1 where the source lies beyond a
-    // wall): all addresses first, then all loads, then the arithmetic, so
-    // that the loads of a node are in flight together
-    int src[L::Q];
+    const bool inner_yz = y >= 3 && y < p.ny - 3 && (L::D == 2 || (z >= 3 && z < p.nz - 3));
+    const bool inner = inner_yz && x >= 3 && x < p.nx - 3;
+    // All addresses first, then all loads, then the arithmetic, so that the
+    // 2Q loads of a node are in flight together.  The three cases are taken
+    // per wavefront: every lane away from the edges (a wave-uniform base per
+    // population and one shared lane offset), only the x edge in reach (a
+    // periodic correction of x per population), or the general wrap with
+    // the wall bookkeeping.
+    T raw[L::Q];
+    uint32_t fw[L::Q];
     uint64_t unk = 0;
-    if (inner) {
+    if (__all(inner)) {
+        const unsigned cb = (unsigned)cell * (unsigned)sizeof(T), cf = (unsigned)cell * 4u;
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i) src[i] = cell - ((L::cz[i] * p.ny + L::cy[i]) * p.nx + L::cx[i]);
+        for (int i = 0; i < L::Q; ++i) {
+            const int shift = (L::cz[i] * p.ny + L::cy[i]) * p.nx + L::cx[i];
+            raw[i] = load_at(fin + ((long long)i * p.pitch - shift), cb);
+            fw[i] = load_at(fp - shift, cf);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    } else if (__all(inner_yz)) {
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            int src = cell - ((L::cz[i] * p.ny + L::cy[i]) * p.nx + L::cx[i]);
+            if (L::cx[i] > 0 && x < L::cx[i]) src += p.nx;
+            if (L::cx[i] < 0 && x >= p.nx + L::cx[i]) src -= p.nx;
+            raw[i] = load_at(fin + (long long)i * p.pitch, (unsigned)src * (unsigned)sizeof(T));
+            fw[i] = load_at(fp, (unsigned)src * 4u);
+        }
+        __builtin_amdgcn_sched_barrier(0);
     } else {
+        const bool walls = WALLS && p.walls;
         int xs[7], ys[7], zs[7];
 #pragma unroll
         for (int k = 0; k < 7; ++k) {
@@ -70,20 +98,14 @@ __device__ __forceinline__ uint64_t pull_cell(const KParams& p, const typename C
                 const int nw = (L::D == 2) ? p.ny : p.nz;
                 known = (kw >= 0 && kw < nw);
             }
-            src[i] = known ? (sz * p.ny + sy) * p.nx + sx : -1;
+            // an unknown population reads the node's own slot; the value is discarded
+            const int src = known ? (sz * p.ny + sy) * p.nx + sx : cell;
             if (!known) unk |= 1ull << i;
+            raw[i] = load_at(fin + (long long)i * p.pitch, (unsigned)src * (unsigned)sizeof(T));
+            fw[i] = load_at(fp, (unsigned)src * 4u);
         }
     }
-    T raw[L::Q];
-    uint32_t fw[L::Q];
-#pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-        const int sc = src[i] < 0 ? cell : src[i];  // unknown: any valid slot, value discarded
-        raw[i] = fin[(long long)i * p.pitch + sc];
-        fw[i] = fp[sc];
-    }
-    // keep the scheduler from sinking loads into the arithmetic below: all
-    // 2Q loads of the node are issued before the first one is consumed
+    // keep the scheduler from sinking loads into the arithmetic below
     __builtin_amdgcn_sched_barrier(0);
     fo = unpack_frame(fw[0]);
     const FrameRef<L> ref = frame_ref<L>(fo);
@@ -91,7 +113,7 @@ __device__ __forceinline__ uint64_t pull_cell(const KParams& p, const typename C
 #pragma unroll
     for (int i = 1; i < L::Q; ++i) {
         const float v = Codec<ST>::dec(raw[i], p.dref[i]) + frame_shift<L>(ref, L::shell[i], unpack_frame(fw[i]));
-        f[i] = ((unk >> i) & 1ull) ? 0.0f : v;
+        f[i] = (WALLS && ((unk >> i) & 1ull)) ? 0.0f : v;
     }
     return unk;
 }

@@ -50,6 +50,9 @@ inline holb_status validate(const holb_config* c)
         return fail(HOLB_EINVAL, "abi_version %d != %d", c->abi_version, HOLB_ABI_VERSION);
     if (c->lattice != HOLB_D2Q37 && c->lattice != HOLB_D3Q39) return fail(HOLB_EINVAL, "unknown lattice %d", c->lattice);
     if (c->nx < 1 || c->ny < 1 || c->nz < 1) return fail(HOLB_EINVAL, "grid dims must be >= 1");
+    // lane offsets within a population plane are 32-bit byte offsets
+    if ((long long)c->nx * c->ny * c->nz > (1ll << 29))
+        return fail(HOLB_ESIZE, "grid of %lld cells exceeds 2^29", (long long)c->nx * c->ny * c->nz);
     if (c->lattice == HOLB_D2Q37 && c->nz != 1) return fail(HOLB_EINVAL, "D2Q37 needs nz == 1");
     const double N = (double)c->nx * c->ny * c->nz;
     if (N > 2147483647.0 / 1.0 || N * 39.0 > 9.0e15) return fail(HOLB_EINVAL, "grid too large");
@@ -103,6 +106,9 @@ inline KParams params_of(const holb_config* c)
     p.walls = c->walls;
     p.N = c->nx * c->ny * c->nz;
     p.nlayer = D == 2 ? c->nx : c->nx * c->ny;
+    p.div_nx = make_fastdiv((unsigned)c->nx);
+    p.div_ny = make_fastdiv((unsigned)c->ny);
+    p.div_layer = make_fastdiv((unsigned)p.nlayer);
     p.flags = ((c->sources & HOLB_SRC_BODY) ? KF_BODY : 0u) | (c->isothermal ? KF_ISO : 0u);
     p.omega = (float)(1.0 / c->tau_hat);
     p.kappa = (float)(1.0 - 1.0 / (2.0 * c->tau_hat));

@@ -51,7 +51,7 @@ struct PlaneSet {
 
 __device__ __forceinline__ int plane_cell(const KParams& p, const PlaneSet& ps, int c)
 {
-    const int k = c / p.nlayer, r = c - k * p.nlayer;
+    const int k = (int)fastdiv((unsigned)c, p.div_layer), r = c - k * p.nlayer;
     const int plane = k < ps.n0 ? ps.lo0 + k : ps.lo1 + (k - ps.n0);
     return plane * p.nlayer + r;
 }

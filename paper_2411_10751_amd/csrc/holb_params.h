@@ -17,11 +17,36 @@ enum : unsigned { HOLB_ERR_DENSITY_BIT = 1u, HOLB_ERR_THETA_BIT = 2u, HOLB_ERR_E
 
 constexpr int QMAX = 39;
 
+// Division by a runtime constant d >= 1 for dividends n < 2^31, as a
+// multiply-high, an add and a shift: with l = ceil(log2 d) and
+// m = floor(2^32 (2^l - d) / d) + 1, n / d = (mulhi(n, m) + n) >> l
+// (the round-up method of Granlund and Montgomery, 1994).
+struct FastDiv {
+    unsigned m, l, d;
+};
+
+inline FastDiv make_fastdiv(unsigned d)
+{
+    FastDiv f;
+    f.d = d;
+    f.l = 0;
+    while ((1ull << f.l) < d) ++f.l;
+    f.m = (unsigned)(((1ull << 32) * ((1ull << f.l) - d)) / d + 1);
+    return f;
+}
+
+__host__ __device__ inline unsigned fastdiv(unsigned n, const FastDiv& f)
+{
+    const unsigned t = (unsigned)(((unsigned long long)n * f.m) >> 32);
+    return (t + n) >> f.l;
+}
+
 struct KParams {
     int nx, ny, nz;      // grid
     int walls;           // 1: TMS walls normal to the last axis
     int N;               // cells
     int nlayer;          // cells per wall-normal layer (nx for 2D, nx*ny for 3D)
+    FastDiv div_nx, div_ny, div_layer;
     long long pitch;     // elements per population plane
     unsigned flags;      // KF_*
     float omega, kappa;  // 1/tau_hat and 1 - 1/(2 tau_hat)

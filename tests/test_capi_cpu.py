@@ -4,6 +4,7 @@ derivation, and configuration/argument errors are reported."""
 import ctypes
 import os
 import re
+import subprocess
 
 import numpy as np
 import pytest
@@ -68,6 +69,7 @@ def _cfg(**kw):
     (dict(storage=1, rho0=0.0), holb.EINVAL),
     (dict(walls=1, ny=6), holb.EINVAL),
     (dict(g=(float("inf"), 0, 0)), holb.EINVAL),
+    (dict(lattice=1, nx=1024, ny=1024, nz=1024), holb.ESIZE),
 ])
 def test_config_errors(bad, code):
     with pytest.raises(holb.HolbError) as ei:
@@ -132,3 +134,38 @@ def test_batch_validation_host_only():
                                    holb.make_config(dict(runs[1]["config"], sources=1)))
     assert holb.holb_batch_workspace_size(mixed, 2, ctypes.byref(n)) == holb.EUNSUPPORTED
     assert holb.holb_batch_workspace_size(arr, 0, ctypes.byref(n)) == holb.EINVAL
+
+
+def test_fastdiv_exact(tmp_path):
+    """The division by a runtime constant used for cell coordinates equals
+    integer division for every divisor up to 4096 and, for large divisors,
+    on dividends spread over [0, 2^31)."""
+    src = tmp_path / "fd.cpp"
+    src.write_text(r'''
+#include <cstdio>
+#include "holb_params.h"
+using namespace holb;
+int main() {
+    unsigned long long bad = 0;
+    for (unsigned d = 1; d <= 4096; ++d) {
+        const FastDiv f = make_fastdiv(d);
+        for (unsigned n = 0; n < 300000; ++n) bad += fastdiv(n, f) != n / d;
+        for (unsigned n = (1u << 31) - 70000; n < (1u << 31); ++n) bad += fastdiv(n, f) != n / d;
+    }
+    unsigned s = 12345u;
+    for (int k = 0; k < 2000000; ++k) {
+        s = s * 1664525u + 1013904223u;
+        const unsigned d = (s >> 1) % ((1u << 30) - 1) + 1;
+        s = s * 1664525u + 1013904223u;
+        const unsigned n = s >> 1;
+        bad += fastdiv(n, make_fastdiv(d)) != n / d;
+    }
+    printf("%llu\n", bad);
+    return bad != 0;
+}
+''')
+    exe = tmp_path / "fd"
+    inc = os.path.join(ROOT, "paper_2411_10751_amd", "csrc")
+    subprocess.run(["g++", "-O2", "-D__host__=", "-D__device__=", "-I" + inc, str(src), "-o", str(exe)], check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0 and r.stdout.strip() == "0", r.stdout

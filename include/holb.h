@@ -203,6 +203,13 @@ holb_status holb_batch_fields(holb_batch* b, int32_t run, float* rho, float* u, 
 holb_status holb_batch_reduce(holb_batch* b, int32_t run, double out[5]);
 holb_status holb_batch_tune(holb_batch* b, int32_t* variant_out);
 holb_status holb_batch_set_variant(holb_batch* b, int32_t variant);
+/* Instrumentation, as holb_timing_start / holb_timing_stop: while a timing is
+ * open, holb_batch_step runs its steps eagerly (no graph replay) and records
+ * a pair of HIP events around each collision launch (k_batch_step, all runs;
+ * cells_per_launch is the total cell count of the batch). */
+holb_status holb_batch_timing_start(holb_batch* b, int32_t max_steps);
+holb_status holb_batch_timing_stop(holb_batch* b, double* kernel_ms, int64_t* launches, int64_t* cells_per_launch,
+                                   char* kernel, size_t kernel_len);
 holb_status holb_batch_destroy(holb_batch* b);
 
 #ifdef __cplusplus

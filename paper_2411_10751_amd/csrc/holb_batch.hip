@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <new>
 #include <vector>
 
@@ -116,6 +117,7 @@ struct holb_batch {
     }
     ~holb_batch()
     {
+        drop_timing();
         drop_graphs();
         if (cap) (void)hipStreamDestroy(cap);
     }
@@ -133,7 +135,9 @@ struct holb_batch {
         return std::max(1, std::min((int)items.size(), 256 * per_cu));
     }
 
-    hipError_t step_once(hipStream_t s, int from) const
+    // One step: the temperature pass (thermal family), then the collision
+    // kernel, optionally between the two timing events.
+    hipError_t step_once(hipStream_t s, int from, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) const
     {
         const int nit = (int)items.size();
         const float* fin = pop(from);
@@ -143,15 +147,31 @@ struct holb_batch {
                                nit, fin, aux(), (const float*)nullptr, err());
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
+        }
+        if (ev0) {
+            hipError_t e = hipEventRecord(ev0, s);
+            if (e != hipSuccess) return e;
+        }
+        if (fam == FAM_THERMAL)
             hipLaunchKernelGGL(k_batch_step<FAM_THERMAL>, dim3(grid()), dim3(BATCH_ITEM), 0, s, d_runs(),
                                d_items(), nit, fin, fout, (const float*)aux(), (const double*)nullptr,
                                (const float*)nullptr, (float*)nullptr, err());
-        } else {
+        else
             hipLaunchKernelGGL(k_batch_step<FAM_LOCAL>, dim3(grid()), dim3(BATCH_ITEM), 0, s, d_runs(), d_items(),
                                nit, fin, fout, (const float*)aux(), (const double*)nullptr, (const float*)nullptr,
                                (float*)nullptr, err());
-        }
-        return hipGetLastError();
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
+        return e;
+    }
+
+    std::vector<hipEvent_t> timing;  // event pairs of the timed steps
+    size_t timed = 0;
+    void drop_timing()
+    {
+        for (hipEvent_t ev : timing) (void)hipEventDestroy(ev);
+        timing.clear();
+        timed = 0;
     }
 
     LaunchCtx run_ctx(int r) const
@@ -339,6 +359,21 @@ holb_status holb_batch_step(holb_batch* b, int64_t n)
     if (!b) return fail(HOLB_EINVAL, "handle is NULL");
     if (n < 0) return fail(HOLB_EINVAL, "n must be >= 0");
     if (!b->initialized) return fail(HOLB_ESTATE, "holb_batch_step before holb_batch_init");
+    if (!b->timing.empty()) {
+        // timed steps run eagerly, each collision launch between two events
+        for (int64_t k = 0; k < n; ++k) {
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (2 * (b->timed + 1) <= b->timing.size()) {
+                e0 = b->timing[2 * b->timed];
+                e1 = b->timing[2 * b->timed + 1];
+                ++b->timed;
+            }
+            hipError_t e = b->step_once(b->stream, b->cur, e0, e1);
+            if (e != hipSuccess) return hip_fail(e, "batched step");
+            b->cur = 1 - b->cur;
+        }
+        return HOLB_OK;
+    }
     if (n >= 2) {
         holb_status s = ensure_graph(b, b->cur);
         if (s) return s;
@@ -385,6 +420,48 @@ holb_status holb_batch_set_variant(holb_batch* b, int32_t variant)
     if (variant != 0 && variant != 2) return fail(HOLB_EUNSUPPORTED, "variant %d not available", variant);
     if (variant != b->variant) b->drop_graphs();
     b->variant = variant;
+    return HOLB_OK;
+}
+
+holb_status holb_batch_timing_start(holb_batch* b, int32_t max_steps)
+{
+    if (!b) return fail(HOLB_EINVAL, "handle is NULL");
+    if (max_steps < 1 || max_steps > 100000) return fail(HOLB_EINVAL, "max_steps must be in [1, 100000]");
+    b->drop_timing();
+    b->timing.resize(2 * (size_t)max_steps, nullptr);
+    for (auto& ev : b->timing) {
+        hipError_t e = hipEventCreate(&ev);
+        if (e != hipSuccess) {
+            ev = nullptr;
+            b->drop_timing();
+            return hip_fail(e, "hipEventCreate");
+        }
+    }
+    return HOLB_OK;
+}
+
+holb_status holb_batch_timing_stop(holb_batch* b, double* kernel_ms, int64_t* launches, int64_t* cells_per_launch,
+                                   char* kernel, size_t kernel_len)
+{
+    if (!b) return fail(HOLB_EINVAL, "handle is NULL");
+    double total = 0.0;
+    hipError_t e = hipSuccess;
+    if (b->timed) e = hipEventSynchronize(b->timing[2 * b->timed - 1]);
+    for (size_t k = 0; k < b->timed && e == hipSuccess; ++k) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, b->timing[2 * k], b->timing[2 * k + 1]);
+        total += ms;
+    }
+    const int64_t n = (int64_t)b->timed;
+    b->drop_timing();
+    if (e != hipSuccess) return hip_fail(e, "reading the timing events");
+    long long cells = 0;
+    for (const RunDesc& r : b->runs) cells += r.N;
+    if (kernel && kernel_len)
+        snprintf(kernel, kernel_len, "k_batch_step<%d>", b->fam);
+    if (kernel_ms) *kernel_ms = total;
+    if (launches) *launches = n;
+    if (cells_per_launch) *cells_per_launch = cells;
     return HOLB_OK;
 }
 

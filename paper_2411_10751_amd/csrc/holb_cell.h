@@ -118,6 +118,51 @@ __device__ __forceinline__ uint64_t pull_cell(const KParams& p, const typename C
     return unk;
 }
 
+// Periodic pull of the populations of node (x, y, z) without their frames
+// (for kernels that hold the frames of the neighbourhood in LDS).  Same three
+// wave-uniform address cases as pull_cell.
+template <class L, int ST>
+__device__ __forceinline__ void pull_raw(const KParams& p, const typename Codec<ST>::T* __restrict__ fin, int x,
+                                         int y, int z, typename Codec<ST>::T (&raw)[L::Q])
+{
+    using T = typename Codec<ST>::T;
+    const int cell = (z * p.ny + y) * p.nx + x;
+    const bool inner_yz = y >= 3 && y < p.ny - 3 && (L::D == 2 || (z >= 3 && z < p.nz - 3));
+    const bool inner = inner_yz && x >= 3 && x < p.nx - 3;
+    if (__all(inner)) {
+        const unsigned cb = (unsigned)cell * (unsigned)sizeof(T);
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            const int shift = (L::cz[i] * p.ny + L::cy[i]) * p.nx + L::cx[i];
+            raw[i] = load_at(fin + ((long long)i * p.pitch - shift), cb);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    } else if (__all(inner_yz)) {
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            int src = cell - ((L::cz[i] * p.ny + L::cy[i]) * p.nx + L::cx[i]);
+            if (L::cx[i] > 0 && x < L::cx[i]) src += p.nx;
+            if (L::cx[i] < 0 && x >= p.nx + L::cx[i]) src -= p.nx;
+            raw[i] = load_at(fin + (long long)i * p.pitch, (unsigned)src * (unsigned)sizeof(T));
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    } else {
+        int xs[7], ys[7], zs[7];
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+            xs[k] = wrapc(x + k - 3, p.nx);
+            ys[k] = wrapc(y + k - 3, p.ny);
+            zs[k] = (L::D == 3) ? wrapc(z + k - 3, p.nz) : 0;
+        }
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            const int src = (zs[3 - L::cz[i]] * p.ny + ys[3 - L::cy[i]]) * p.nx + xs[3 - L::cx[i]];
+            raw[i] = load_at(fin + (long long)i * p.pitch, (unsigned)src * (unsigned)sizeof(T));
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 // Store the post-collision populations of a node in a new frame fn (written
 // to the frame plane of fout): h_i(fn) = h_i(fo) + R_i(fo) - R_i(fn), one
 // shift per shell.

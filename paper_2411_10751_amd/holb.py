@@ -83,6 +83,9 @@ _sig = {
     "holb_tune": ([_vp, _P(ctypes.c_int32)], ctypes.c_int32),
     "holb_set_variant": ([_vp, ctypes.c_int32], ctypes.c_int32),
     "holb_timing_start": ([_vp, ctypes.c_int32], ctypes.c_int32),
+    "holb_batch_timing_start": ([_vp, ctypes.c_int32], ctypes.c_int32),
+    "holb_batch_timing_stop": ([_vp, _P(ctypes.c_double), _P(ctypes.c_int64), _P(ctypes.c_int64), ctypes.c_char_p,
+                                ctypes.c_size_t], ctypes.c_int32),
     "holb_timing_stop": ([_vp, _P(ctypes.c_double), _P(ctypes.c_int64), _P(ctypes.c_int64), ctypes.c_char_p,
                           ctypes.c_size_t], ctypes.c_int32),
     "holb_num_variants": ([_vp, _P(ctypes.c_int32)], ctypes.c_int32),
@@ -358,3 +361,15 @@ class Batch:
 
     def set_variant(self, v):
         check(holb_batch_set_variant(self._h, int(v)), "holb_batch_set_variant")
+
+    def timing_start(self, max_steps):
+        check(holb_batch_timing_start(self._h, int(max_steps)), "holb_batch_timing_start")
+
+    def timing_stop(self):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        cells = ctypes.c_int64()
+        name = ctypes.create_string_buffer(256)
+        check(holb_batch_timing_stop(self._h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(cells), name, 256),
+              "holb_batch_timing_stop")
+        return ms.value, n.value, cells.value, name.value.decode()

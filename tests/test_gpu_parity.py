@@ -414,12 +414,16 @@ def test_batched_graph_replay_matches_eager():
 # ----------------------------------------------------------------- variants
 
 
-@pytest.mark.parametrize("wname", ["rb3d", "thermal2d", "body2d", "ptensor2d"])
+@pytest.mark.parametrize("wname", ["rb3d", "rb3d_tall", "periodic3d", "thermal2d", "body2d", "ptensor2d"])
 def test_variants_bitwise_identical(wname):
-    """Every kernel variant of a configuration gives bitwise identical fields."""
+    """Every kernel variant of a configuration gives bitwise identical fields
+    (tall boxes span several chunks of the plane-marching kernels; lateral
+    sizes that are no multiple of the tiles leave ragged tiles)."""
     import torch
     from paper_2411_10751_amd import holb
     w = {"rb3d": lambda: _rb(40, 24, 6),
+         "rb3d_tall": lambda: _rb(36, 150, 3),
+         "periodic3d": lambda: _rb(36, 70, 3, walls=0),
          "thermal2d": lambda: inputs.thermal_2d(n=300, steps=6),
          "body2d": lambda: inputs.body_force_2d(n=130, steps=6),
          "ptensor2d": lambda: inputs.ptensor_2d(n=200, steps=6, ndrops=4, rmin=10, rmax=20)}[wname]()

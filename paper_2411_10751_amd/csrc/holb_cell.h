@@ -8,14 +8,23 @@
 
 namespace holb {
 
-// Block index remapped so that the eight XCDs (which receive blocks
-// round-robin) each get a contiguous range of cells, keeping the pull
-// neighbourhood of a block in the same L2.
-__device__ __forceinline__ int xcd_block()
+// Order in which blocks take cells.  The eight XCDs receive blocks round-
+// robin (block b runs on XCD b % 8), each with its own L2.
+//   band = 0: cell order -- the chip sweeps the domain plane by plane;
+//   band < 0: each XCD gets a contiguous eighth of the cells;
+//   band = G > 0: the chip still sweeps plane by plane, but each XCD takes
+//     runs of G consecutive blocks (a band of rows of the plane), so the
+//     rows a pull reaches mostly sit in the same L2.
+// Orders other than 0 need a block count that is a multiple of 8 (of 8 G for
+// bands); otherwise cell order is used.
+__device__ __forceinline__ int xcd_block(int band = -1)
 {
     const int nb = gridDim.x, b = blockIdx.x;
-    if (nb % 8) return b;
-    return (b % 8) * (nb / 8) + b / 8;
+    if (band == 0 || nb % 8) return b;
+    if (band < 0) return (b % 8) * (nb / 8) + b / 8;
+    if (nb % (8 * band)) return b;
+    const int j = b / 8, x = b % 8;
+    return ((j / band) * 8 + x) * band + j % band;
 }
 
 template <class L>

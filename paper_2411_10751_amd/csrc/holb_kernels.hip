@@ -59,9 +59,9 @@ __device__ __forceinline__ int plane_cell(const KParams& p, const PlaneSet& ps, 
 template <class L, int ST, int FAM, bool WALLS>
 __global__ void __launch_bounds__(GEN_BLOCK)
 k_aux(const KParams p, const PlaneSet ps, const typename Codec<ST>::T* __restrict__ fin,
-      const float* __restrict__ tgt_in, float* __restrict__ aux_f, double* __restrict__ aux_d)
+      const float* __restrict__ tgt_in, float* __restrict__ aux_f, double* __restrict__ aux_d, int remap)
 {
-    const int c = xcd_block() * GEN_BLOCK + threadIdx.x;
+    const int c = xcd_block(remap) * GEN_BLOCK + threadIdx.x;
     if (c < (ps.n0 + ps.n1) * p.nlayer)
         aux_cell<L, ST, FAM, WALLS>(p, fin, tgt_in, aux_f, aux_d, plane_cell(p, ps, c));
 }
@@ -70,9 +70,9 @@ template <class L, int ST, int FAM, bool WALLS>
 __global__ void __launch_bounds__(GEN_BLOCK)
 k_step(const KParams p, const PlaneSet ps, const typename Codec<ST>::T* __restrict__ fin,
        typename Codec<ST>::T* __restrict__ fout, const float* __restrict__ aux_f, const double* __restrict__ aux_d,
-       const float* __restrict__ tgt_in, float* __restrict__ tgt_out)
+       const float* __restrict__ tgt_in, float* __restrict__ tgt_out, int remap)
 {
-    const int c = xcd_block() * GEN_BLOCK + threadIdx.x;
+    const int c = xcd_block(remap) * GEN_BLOCK + threadIdx.x;
     if (c < (ps.n0 + ps.n1) * p.nlayer)
         step_cell<L, ST, FAM, WALLS>(p, fin, fout, aux_f, aux_d, tgt_in, tgt_out, plane_cell(p, ps, c));
 }
@@ -179,6 +179,18 @@ struct Launch {
     using T = typename Codec<ST>::T;
 
     static int nm(const KParams& p) { return L::D == 3 ? p.nz : p.ny; }
+    // generic kernels: variant 0 cell order, 1 XCD-contiguous eighths, 2 plane
+    // bands per XCD (argument of xcd_block); >= 3: marching kernels
+    static int remap(const LaunchCtx& c)
+    {
+        if (c.variant == 1) return -1;
+        if (c.variant == 2) {
+            const int bpp = c.kp.nlayer / GEN_BLOCK;  // blocks per plane
+            return (c.kp.nlayer % GEN_BLOCK == 0 && bpp % 8 == 0) ? bpp / 8 : 0;
+        }
+        return 0;
+    }
+    static bool marching(const LaunchCtx& c) { return c.variant >= 3 && march_variant_supported(c, c.variant); }
     static PlaneSet all(const KParams& p) { return PlaneSet{0, nm(p), 0, 0}; }
 
     static hipError_t init(const LaunchCtx& c, const float* rho, const float* u, const float* th)
@@ -201,10 +213,10 @@ struct Launch {
         const dim3 grid(nblocks_for(n));
         if (walls)
             hipLaunchKernelGGL((k_aux<L, ST, FAM, true>), grid, dim3(GEN_BLOCK), 0, c.stream, c.kp, ps,
-                               (const T*)c.pop_in, c.tgt_in, c.aux_f, c.aux_d);
+                               (const T*)c.pop_in, c.tgt_in, c.aux_f, c.aux_d, remap(c));
         else
             hipLaunchKernelGGL((k_aux<L, ST, FAM, false>), grid, dim3(GEN_BLOCK), 0, c.stream, c.kp, ps,
-                               (const T*)c.pop_in, c.tgt_in, c.aux_f, c.aux_d);
+                               (const T*)c.pop_in, c.tgt_in, c.aux_f, c.aux_d, remap(c));
         return hipGetLastError();
     }
 
@@ -215,10 +227,10 @@ struct Launch {
         const dim3 grid(nblocks_for(n));
         if (walls)
             hipLaunchKernelGGL((k_step<L, ST, FAM, true>), grid, dim3(GEN_BLOCK), 0, c.stream, c.kp, ps,
-                               (const T*)c.pop_in, (T*)c.pop_out, c.aux_f, c.aux_d, c.tgt_in, c.tgt_out);
+                               (const T*)c.pop_in, (T*)c.pop_out, c.aux_f, c.aux_d, c.tgt_in, c.tgt_out, remap(c));
         else
             hipLaunchKernelGGL((k_step<L, ST, FAM, false>), grid, dim3(GEN_BLOCK), 0, c.stream, c.kp, ps,
-                               (const T*)c.pop_in, (T*)c.pop_out, c.aux_f, c.aux_d, c.tgt_in, c.tgt_out);
+                               (const T*)c.pop_in, (T*)c.pop_out, c.aux_f, c.aux_d, c.tgt_in, c.tgt_out, remap(c));
         return hipGetLastError();
     }
 
@@ -252,7 +264,7 @@ struct Launch {
     static hipError_t step(const LaunchCtx& c)
     {
         const int n = nm(c.kp);
-        if (c.variant != 0 && march_variant_supported(c, c.variant)) {
+        if (marching(c)) {
             if (!c.kp.walls) return timed(c, [&] { return march_step<L, ST, FAM>(c, 0, n); });
             // wall layers by the generic kernels: theta of the four planes
             // next to each wall, then the collision of the three wall
@@ -274,12 +286,12 @@ struct Launch {
     static void dominant(const LaunchCtx& c, char* name, size_t len, long long* cells)
     {
         const int n = nm(c.kp);
-        const bool march = c.variant != 0 && march_variant_supported(c, c.variant);
+        const bool march = marching(c);
         const int planes = c.kp.walls ? n - 6 : n;
         if (cells) *cells = (long long)planes * c.kp.nlayer;
         if (!name || !len) return;
         const char* lat = L::D == 3 ? "D3Q39" : "D2Q37";
-        if (march) march_kernel_name<L>(c.variant, lat, ST, name, len);
+        if (march) march_kernel_name<L>(c.variant - 2, lat, ST, name, len);
         else snprintf(name, len, "k_step<%s,%d,%d,false>", lat, ST, FAM);
     }
 
@@ -403,11 +415,11 @@ void dominant_kernel(const LaunchCtx& c, char* name, size_t len, long long* cell
     else dominant_storage<D3Q39>(c, name, len, cells);
 }
 
-int num_variants(const LaunchCtx& c) { return 1 + march_num_variants(c); }
+int num_variants(const LaunchCtx& c) { return 3 + march_num_variants(c); }
 
 bool variant_supported(const LaunchCtx& c, int variant)
 {
-    if (variant == 0) return true;
+    if (variant >= 0 && variant <= 2) return true;
     return march_variant_supported(c, variant);
 }
 

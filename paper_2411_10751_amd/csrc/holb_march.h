@@ -272,8 +272,10 @@ inline int march_num_variants(const LaunchCtx& c)
     return c.lattice == 1 ? MarchVariants<D3Q39>::N : MarchVariants<D2Q37>::N;
 }
 
-inline bool march_variant_supported(const LaunchCtx& c, int v)
+// Library variants 3.. are the marching kernels 1.. of the table below.
+inline bool march_variant_supported(const LaunchCtx& c, int lib_variant)
 {
+    const int v = lib_variant - 2;
     if (c.family != FAM_THERMAL || v < 1) return false;
     const int nm = c.lattice == 1 ? c.kp.nz : c.kp.ny;
     const int nlat = c.kp.nx;
@@ -302,13 +304,13 @@ hipError_t march_step(const LaunchCtx& c, int mlo, int mhi)
 {
     if (FAM != FAM_THERMAL || !march_variant_supported(c, c.variant)) return hipErrorNotSupported;
     if constexpr (L::D == 3) {
-        switch (c.variant) {
+        switch (c.variant - 2) {
         case 1: return launch_march_shape<L, ST, MarchShape<34, 14, 2>, 3>(c, 32, mlo, mhi);
         case 2: return launch_march_shape<L, ST, MarchShape<34, 10, 2>, 3>(c, 64, mlo, mhi);
         case 3: return launch_march_shape<L, ST, MarchShape<34, 10, 3>, 4>(c, 32, mlo, mhi);
         }
     } else {
-        switch (c.variant) {
+        switch (c.variant - 2) {
         case 1: return launch_march_shape<L, ST, MarchShape<258, 1, 2>, 3>(c, 64, mlo, mhi);
         case 2: return launch_march_shape<L, ST, MarchShape<130, 1, 2>, 3>(c, 32, mlo, mhi);
         case 3: return launch_march_shape<L, ST, MarchShape<130, 1, 3>, 4>(c, 32, mlo, mhi);

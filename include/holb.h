@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define HOLB_ABI_VERSION 1
+#define HOLB_ABI_VERSION 2
 
 typedef int32_t holb_status;
 #define HOLB_OK 0
@@ -68,6 +68,19 @@ typedef int32_t holb_status;
  * equilibrium of their cell's frame, divided by w_i.  The 16-bit forms also
  * subtract the bracket of the uniform background velocity u0 and round to
  * nearest-even (see holb_get_state for the exact format). */
+/* Frames (the reference the stored populations are deviations from, see
+ * holb_get_state).  CELL keeps each cell's density and temperature of the
+ * last step beside its populations (4 bytes per cell, read with every pull).
+ * PLANE keeps one fixed frame per plane along the last axis (the plane means
+ * of the initial fields): nothing per cell, and suited to states whose
+ * density and temperature vary mostly along that axis -- it keeps less of the
+ * FP32 precision where the state drifts far from those means.  PLANE is FP32
+ * only.  AUTO picks PLANE for FP32 storage with walls (which impose the mean
+ * profile along the wall-normal axis) and CELL otherwise. */
+#define HOLB_FRAMES_AUTO 0
+#define HOLB_FRAMES_CELL 1
+#define HOLB_FRAMES_PLANE 2
+
 #define HOLB_STORE_F32 0
 #define HOLB_STORE_F16DEV 1
 #define HOLB_STORE_BF16DEV 2
@@ -96,6 +109,7 @@ typedef struct {
     int32_t walls;        /* 0: periodic; 1: TMS walls (Eqs. 4.7-4.8) normal to the last axis */
     double theta_wall[2]; /* wall temperatures: [0] at index 0, [1] at index n-1 */
     double u_wall[2][3];  /* wall velocities, same order */
+    int32_t frames;       /* HOLB_FRAMES_*: reference of the stored populations */
 } holb_config;
 
 typedef struct holb_sim holb_sim;

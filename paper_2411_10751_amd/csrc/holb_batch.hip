@@ -14,7 +14,6 @@
 #include "holb_cell.h"
 #include "holb_host.h"
 #include "holb_internal.h"
-#include "holb_march.h"
 
 using namespace holb;
 
@@ -23,7 +22,8 @@ namespace holb {
 struct RunDesc {
     int nx, ny, N;
     unsigned flags;
-    long long off;     // element offset of the run's planes (Q, then frames) in a population buffer
+    long long off;     // element offset of the run's Q planes in a population buffer
+    long long tab;     // float offset of the run's per-plane frames and shifts in the table region
     long long pitch;   // elements per population plane of this run
     long long cell0;   // offset of the run's cells in the theta field
     float omega, kappa, g0, g1, hfac;
@@ -34,7 +34,7 @@ struct RunDesc {
 
 constexpr int BATCH_ITEM = 256;
 
-__device__ __forceinline__ KParams run_params(const RunDesc& r, unsigned* err)
+__device__ __forceinline__ KParams run_params(const RunDesc& r, unsigned* err, const float* tab)
 {
     KParams p = {};
     p.nx = r.nx; p.ny = r.ny; p.nz = 1;
@@ -52,21 +52,24 @@ __device__ __forceinline__ KParams run_params(const RunDesc& r, unsigned* err)
     p.rho_ref = r.rho_ref;
     p.thb_ref = r.thb_ref;
     p.err = err;
+    p.plane_frame = tab + r.tab;
+    p.plane_shift = tab + r.tab + 2 * r.ny;
     return p;
 }
 
 template <int FAM>
 __global__ void __launch_bounds__(BATCH_ITEM)
 k_batch_aux(const RunDesc* __restrict__ runs, const int2* __restrict__ items, int nitems,
-            const float* __restrict__ fin, float* __restrict__ aux, const float* __restrict__ tgi, unsigned* err)
+            const float* __restrict__ fin, float* __restrict__ aux, const float* __restrict__ tgi, unsigned* err,
+            const float* __restrict__ tab)
 {
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const int2 t = items[it];
         const RunDesc r = runs[t.x];
         const int cell = t.y + threadIdx.x;
         if (cell < r.N) {
-            const KParams p = run_params(r, err);
-            aux_cell<D2Q37, ST_F32, FAM, false>(p, fin + r.off, tgi, aux + r.cell0, nullptr, cell);
+            const KParams p = run_params(r, err, tab);
+            aux_cell<D2Q37, ST_F32, FAM, false, FM_PLANE>(p, fin + r.off, tgi, aux + r.cell0, nullptr, cell);
         }
     }
 }
@@ -75,15 +78,17 @@ template <int FAM>
 __global__ void __launch_bounds__(BATCH_ITEM)
 k_batch_step(const RunDesc* __restrict__ runs, const int2* __restrict__ items, int nitems,
              const float* __restrict__ fin, float* __restrict__ fout, const float* __restrict__ aux,
-             const double* __restrict__ auxd, const float* __restrict__ tgi, float* __restrict__ tgo, unsigned* err)
+             const double* __restrict__ auxd, const float* __restrict__ tgi, float* __restrict__ tgo, unsigned* err,
+             const float* __restrict__ tab)
 {
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const int2 t = items[it];
         const RunDesc r = runs[t.x];
         const int cell = t.y + threadIdx.x;
         if (cell < r.N) {
-            const KParams p = run_params(r, err);
-            step_cell<D2Q37, ST_F32, FAM, false>(p, fin + r.off, fout + r.off, aux + r.cell0, auxd, tgi, tgo, cell);
+            const KParams p = run_params(r, err, tab);
+            step_cell<D2Q37, ST_F32, FAM, false, FM_PLANE>(p, fin + r.off, fout + r.off, aux + r.cell0, auxd, tgi, tgo,
+                                                           cell);
         }
     }
 }
@@ -100,6 +105,7 @@ struct holb_batch {
     hipStream_t stream = nullptr;
     size_t pop_off[2] = {0, 0}, pop_elems = 0, aux_off = 0, desc_off = 0, items_off = 0;
     size_t part_off = 0, out_off = 0, err_off = 0, total = 0;
+    size_t tab_off = 0;
     int max_partials = 0;
     int cur = 0;
     bool initialized = false;
@@ -126,6 +132,7 @@ struct holb_batch {
     const int2* d_items() const { return (const int2*)(ws + items_off); }
     float* pop(int k) const { return (float*)(ws + pop_off[k]); }
     float* aux() const { return (float*)(ws + aux_off); }
+    float* tab() const { return (float*)(ws + tab_off); }
     unsigned* err() const { return (unsigned*)(ws + err_off); }
 
     // persistent grid: a few blocks per compute unit, walking the work list
@@ -144,7 +151,7 @@ struct holb_batch {
         float* fout = pop(1 - from);
         if (fam == FAM_THERMAL) {
             hipLaunchKernelGGL(k_batch_aux<FAM_THERMAL>, dim3(grid()), dim3(BATCH_ITEM), 0, s, d_runs(), d_items(),
-                               nit, fin, aux(), (const float*)nullptr, err());
+                               nit, fin, aux(), (const float*)nullptr, err(), (const float*)tab());
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
@@ -155,11 +162,11 @@ struct holb_batch {
         if (fam == FAM_THERMAL)
             hipLaunchKernelGGL(k_batch_step<FAM_THERMAL>, dim3(grid()), dim3(BATCH_ITEM), 0, s, d_runs(),
                                d_items(), nit, fin, fout, (const float*)aux(), (const double*)nullptr,
-                               (const float*)nullptr, (float*)nullptr, err());
+                               (const float*)nullptr, (float*)nullptr, err(), (const float*)tab());
         else
             hipLaunchKernelGGL(k_batch_step<FAM_LOCAL>, dim3(grid()), dim3(BATCH_ITEM), 0, s, d_runs(), d_items(),
                                nit, fin, fout, (const float*)aux(), (const double*)nullptr, (const float*)nullptr,
-                               (float*)nullptr, err());
+                               (float*)nullptr, err(), (const float*)tab());
         hipError_t e = hipGetLastError();
         if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
         return e;
@@ -181,9 +188,12 @@ struct holb_batch {
         c.lattice = HOLB_D2Q37;
         c.storage = ST_F32;
         c.family = fam;
+        c.frames = FM_PLANE;
         c.kp = params_of(&cfgs[r]);
         c.kp.pitch = runs[r].pitch;
         c.kp.err = err();
+        c.kp.plane_frame = tab() + runs[r].tab;
+        c.kp.plane_shift = tab() + runs[r].tab + 2 * runs[r].ny;
         c.pop_in = pop(cur) + runs[r].off;
         c.pop_out = pop(1 - cur) + runs[r].off;
         c.aux_f = aux() + runs[r].cell0;
@@ -205,6 +215,8 @@ holb_status validate_batch(const holb_config* cfgs, int32_t n)
         const holb_config& c = cfgs[r];
         if (c.lattice != HOLB_D2Q37 || c.storage != HOLB_STORE_F32 || c.isothermal || c.walls)
             return fail(HOLB_EUNSUPPORTED, "run %d: batches hold periodic, non-isothermal D2Q37 FP32 runs", r);
+        if (c.frames == HOLB_FRAMES_CELL)
+            return fail(HOLB_EUNSUPPORTED, "run %d: batched runs use per-plane frames", r);
         if (c.sources & HOLB_SRC_PTENSOR) return fail(HOLB_EUNSUPPORTED, "run %d: no pressure tensor in batches", r);
         if (family_of(c.sources) != family_of(cfgs[0].sources))
             return fail(HOLB_EUNSUPPORTED, "run %d: all runs must share the thermal source on/off", r);
@@ -219,7 +231,7 @@ void plan(holb_batch* b, const holb_config* cfgs, int n)
     b->fam = family_of(cfgs[0].sources);
     b->runs.resize(n);
     b->items.clear();
-    size_t elems = 0, cells = 0;
+    size_t elems = 0, cells = 0, tabf = 0;
     int maxblk = 0;
     for (int r = 0; r < n; ++r) {
         const holb_config& c = cfgs[r];
@@ -236,7 +248,9 @@ void plan(holb_batch* b, const holb_config* cfgs, int n)
         d.pitch = (long long)align_up((size_t)d.N, 64);
         d.off = (long long)elems;
         d.cell0 = (long long)cells;
-        elems += (size_t)(D2Q37::Q + 1) * d.pitch;  // Q planes, then the frame plane
+        elems += (size_t)D2Q37::Q * d.pitch;
+        d.tab = (long long)tabf;
+        tabf += (size_t)(2 + 7 * D2Q37::NS) * c.ny;
         cells += align_up((size_t)d.N, 64);
         for (int c0 = 0; c0 < d.N; c0 += BATCH_ITEM) b->items.push_back(make_int2(r, c0));
         maxblk = std::max(maxblk, (d.N + 255) / 256);
@@ -246,6 +260,7 @@ void plan(holb_batch* b, const holb_config* cfgs, int n)
     b->pop_off[0] = off; off = align_up(off + elems * 4);
     b->pop_off[1] = off; off = align_up(off + elems * 4);
     b->aux_off = off; off = align_up(off + cells * 4);
+    b->tab_off = off; off = align_up(off + tabf * 4);
     b->desc_off = off; off = align_up(off + (size_t)n * sizeof(RunDesc));
     b->items_off = off; off = align_up(off + b->items.size() * sizeof(int2));
     b->max_partials = maxblk;

@@ -28,6 +28,8 @@ struct Layout {
     size_t elem = 4;          // bytes per stored population
     size_t pitch = 0;         // elements per population plane
     size_t pop_bytes = 0;     // one population buffer
+    size_t tab_off = 0, tab_bytes = 0;  // per-plane frames and shifts (FP32 storage)
+    int nm = 0;               // planes along the last axis
     size_t pop_off[2] = {0, 0};
     size_t aux_off = 0, aux_bytes = 0;
     size_t tgt_off[2] = {0, 0};
@@ -46,12 +48,17 @@ Layout layout_of(const holb_config* c)
     const size_t N = (size_t)c->nx * c->ny * c->nz;
     L.elem = c->storage == HOLB_STORE_F32 ? 4 : 2;
     L.pitch = align_up(N, ALIGN / L.elem);
-    // Q population planes, then one binary16 pair (rho, theta) per cell: the
-    // frame the cell's populations are stored in
-    L.pop_bytes = (size_t)Q * L.pitch * L.elem + align_up(N * 4);
+    // Q population planes; with per-cell frames, then one binary16 pair (rho,
+    // theta - 1) per cell: the frame the cell's populations are stored in.
+    // Per-plane frames are kept in a table of (2 + 7 NS) floats per plane.
+    const bool per_cell = frames_of(c) == FM_CELL;
+    L.pop_bytes = (size_t)Q * L.pitch * L.elem + (per_cell ? align_up(N * 4) : 0);
+    L.nm = D == 3 ? c->nz : c->ny;
+    L.tab_bytes = per_cell ? 0 : (size_t)(2 + 7 * lattice_NS(c->lattice)) * L.nm * sizeof(float);
     size_t off = 0;
     L.pop_off[0] = off; off = align_up(off + L.pop_bytes);
     L.pop_off[1] = off; off = align_up(off + L.pop_bytes);
+    L.tab_off = off; off = align_up(off + L.tab_bytes);
     const int fam = family_of(c->sources);
     L.aux_bytes = fam == FAM_PTENSOR ? N * 8 : (fam == FAM_THERMAL ? N * 4 : 0);
     L.aux_off = off; off = align_up(off + L.aux_bytes);
@@ -151,9 +158,14 @@ holb_status holb_create(const holb_config* cfg, void* dev_workspace, size_t byte
     c.lattice = cfg->lattice;
     c.storage = cfg->storage;
     c.family = family_of(cfg->sources);
+    c.frames = frames_of(cfg);
     c.kp = params_of(cfg);
     c.kp.err = (unsigned*)(h->ws + L.err_off);
     c.kp.pitch = (long long)L.pitch;
+    if (L.tab_bytes) {
+        c.kp.plane_frame = (const float*)(h->ws + L.tab_off);
+        c.kp.plane_shift = c.kp.plane_frame + 2 * L.nm;
+    }
     c.aux_f = L.aux_bytes ? (float*)(h->ws + L.aux_off) : nullptr;
     c.aux_d = L.aux_bytes ? (double*)(h->ws + L.aux_off) : nullptr;
     c.partials = (double*)(h->ws + L.part_off);
@@ -247,15 +259,18 @@ holb_status holb_error_flags(holb_sim* s, uint32_t* flags)
 holb_status holb_state_bytes(holb_sim* s, size_t* bytes)
 {
     if (!s || !bytes) return fail(HOLB_EINVAL, "NULL argument");
-    *bytes = s->lay.pop_bytes;
+    *bytes = s->lay.pop_bytes + s->lay.tab_bytes;
     return HOLB_OK;
 }
 
 holb_status holb_get_state(holb_sim* s, void* dst, size_t bytes)
 {
     if (!s || !dst) return fail(HOLB_EINVAL, "NULL argument");
-    if (bytes != s->lay.pop_bytes) return fail(HOLB_ESIZE, "state is %zu bytes, got %zu", s->lay.pop_bytes, bytes);
-    hipError_t e = hipMemcpyAsync(dst, s->ws + s->lay.pop_off[s->cur], bytes, hipMemcpyDeviceToDevice, s->stream);
+    const size_t pb = s->lay.pop_bytes, tb = s->lay.tab_bytes;
+    if (bytes != pb + tb) return fail(HOLB_ESIZE, "state is %zu bytes, got %zu", pb + tb, bytes);
+    hipError_t e = hipMemcpyAsync(dst, s->ws + s->lay.pop_off[s->cur], pb, hipMemcpyDeviceToDevice, s->stream);
+    if (e == hipSuccess && tb)
+        e = hipMemcpyAsync((char*)dst + pb, s->ws + s->lay.tab_off, tb, hipMemcpyDeviceToDevice, s->stream);
     if (e != hipSuccess) return hip_fail(e, "copying the state out");
     return HOLB_OK;
 }
@@ -263,9 +278,12 @@ holb_status holb_get_state(holb_sim* s, void* dst, size_t bytes)
 holb_status holb_set_state(holb_sim* s, const void* src, size_t bytes)
 {
     if (!s || !src) return fail(HOLB_EINVAL, "NULL argument");
-    if (bytes != s->lay.pop_bytes) return fail(HOLB_ESIZE, "state is %zu bytes, got %zu", s->lay.pop_bytes, bytes);
+    const size_t pb = s->lay.pop_bytes, tb = s->lay.tab_bytes;
+    if (bytes != pb + tb) return fail(HOLB_ESIZE, "state is %zu bytes, got %zu", pb + tb, bytes);
     if (s->cfg.walls && !s->initialized) return fail(HOLB_ESTATE, "walled domains need holb_init before holb_set_state");
-    hipError_t e = hipMemcpyAsync(s->ws + s->lay.pop_off[s->cur], src, bytes, hipMemcpyDeviceToDevice, s->stream);
+    hipError_t e = hipMemcpyAsync(s->ws + s->lay.pop_off[s->cur], src, pb, hipMemcpyDeviceToDevice, s->stream);
+    if (e == hipSuccess && tb)
+        e = hipMemcpyAsync(s->ws + s->lay.tab_off, (const char*)src + pb, tb, hipMemcpyDeviceToDevice, s->stream);
     if (e != hipSuccess) return hip_fail(e, "copying the state in");
     s->initialized = true;
     return HOLB_OK;

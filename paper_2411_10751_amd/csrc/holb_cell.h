@@ -52,11 +52,21 @@ __device__ __forceinline__ T load_at(const T* __restrict__ base, unsigned byte_o
     return *(const T*)((const char*)base + byte_off);
 }
 
-template <class L, int ST, bool WALLS>
+// Frame of the plane of march-axis coordinate m (FM_PLANE).
+__device__ __forceinline__ Frame plane_frame_of(const KParams& p, int m)
+{
+    Frame F;
+    F.rho = p.plane_frame[2 * m];
+    F.thb = p.plane_frame[2 * m + 1];
+    return F;
+}
+
+template <class L, int ST, bool WALLS, int FM>
 __device__ __forceinline__ uint64_t pull_cell(const KParams& p, const typename Codec<ST>::T* __restrict__ fin,
                                               int x, int y, int z, float (&f)[L::Q], Frame& fo)
 {
     using T = typename Codec<ST>::T;
+    constexpr bool CF = FM == FM_CELL;
     const uint32_t* __restrict__ fp = frame_plane<ST>(fin, p.pitch, L::Q);
     const int cell = (z * p.ny + y) * p.nx + x;
     const bool inner_yz = y >= 3 && y < p.ny - 3 && (L::D == 2 || (z >= 3 && z < p.nz - 3));
@@ -76,7 +86,7 @@ __device__ __forceinline__ uint64_t pull_cell(const KParams& p, const typename C
         for (int i = 0; i < L::Q; ++i) {
             const int shift = (L::cz[i] * p.ny + L::cy[i]) * p.nx + L::cx[i];
             raw[i] = load_at(fin + ((long long)i * p.pitch - shift), cb);
-            fw[i] = load_at(fp - shift, cf);
+            if (CF) fw[i] = load_at(fp - shift, cf);
         }
         __builtin_amdgcn_sched_barrier(0);
     } else if (__all(inner_yz)) {
@@ -86,7 +96,7 @@ __device__ __forceinline__ uint64_t pull_cell(const KParams& p, const typename C
             if (L::cx[i] > 0 && x < L::cx[i]) src += p.nx;
             if (L::cx[i] < 0 && x >= p.nx + L::cx[i]) src -= p.nx;
             raw[i] = load_at(fin + (long long)i * p.pitch, (unsigned)src * (unsigned)sizeof(T));
-            fw[i] = load_at(fp, (unsigned)src * 4u);
+            if (CF) fw[i] = load_at(fp, (unsigned)src * 4u);
         }
         __builtin_amdgcn_sched_barrier(0);
     } else {
@@ -111,84 +121,60 @@ __device__ __forceinline__ uint64_t pull_cell(const KParams& p, const typename C
             const int src = known ? (sz * p.ny + sy) * p.nx + sx : cell;
             if (!known) unk |= 1ull << i;
             raw[i] = load_at(fin + (long long)i * p.pitch, (unsigned)src * (unsigned)sizeof(T));
-            fw[i] = load_at(fp, (unsigned)src * 4u);
+            if (CF) fw[i] = load_at(fp, (unsigned)src * 4u);
         }
     }
     // keep the scheduler from sinking loads into the arithmetic below
     __builtin_amdgcn_sched_barrier(0);
-    fo = unpack_frame(fw[0]);
-    const FrameRef<L> ref = frame_ref<L>(fo);
     f[0] = Codec<ST>::dec(raw[0], p.dref[0]);
+    if constexpr (CF) {
+        fo = unpack_frame(fw[0]);
+        const FrameRef<L> ref = frame_ref<L>(fo);
 #pragma unroll
-    for (int i = 1; i < L::Q; ++i) {
-        const float v = Codec<ST>::dec(raw[i], p.dref[i]) + frame_shift<L>(ref, L::shell[i], unpack_frame(fw[i]));
-        f[i] = (WALLS && ((unk >> i) & 1ull)) ? 0.0f : v;
+        for (int i = 1; i < L::Q; ++i) {
+            const float v = Codec<ST>::dec(raw[i], p.dref[i]) + frame_shift<L>(ref, L::shell[i], unpack_frame(fw[i]));
+            f[i] = (WALLS && ((unk >> i) & 1ull)) ? 0.0f : v;
+        }
+    } else {
+        // plane frames: the shift depends only on the plane, the march-axis
+        // velocity and the shell (zero within the plane)
+        const int m = L::D == 3 ? z : y;
+        fo = plane_frame_of(p, m);
+        const float* __restrict__ sh = p.plane_shift + (long long)m * 7 * L::NS;
+#pragma unroll
+        for (int i = 1; i < L::Q; ++i) {
+            const int cm = L::D == 3 ? L::cz[i] : L::cy[i];
+            float v = Codec<ST>::dec(raw[i], p.dref[i]);
+            if (cm != 0) v += sh[(cm + 3) * L::NS + L::shell[i]];
+            f[i] = (WALLS && ((unk >> i) & 1ull)) ? 0.0f : v;
+        }
     }
     return unk;
 }
 
-// Periodic pull of the populations of node (x, y, z) without their frames
-// (for kernels that hold the frames of the neighbourhood in LDS).  Same three
-// wave-uniform address cases as pull_cell.
-template <class L, int ST>
-__device__ __forceinline__ void pull_raw(const KParams& p, const typename Codec<ST>::T* __restrict__ fin, int x,
-                                         int y, int z, typename Codec<ST>::T (&raw)[L::Q])
-{
-    using T = typename Codec<ST>::T;
-    const int cell = (z * p.ny + y) * p.nx + x;
-    const bool inner_yz = y >= 3 && y < p.ny - 3 && (L::D == 2 || (z >= 3 && z < p.nz - 3));
-    const bool inner = inner_yz && x >= 3 && x < p.nx - 3;
-    if (__all(inner)) {
-        const unsigned cb = (unsigned)cell * (unsigned)sizeof(T);
-#pragma unroll
-        for (int i = 0; i < L::Q; ++i) {
-            const int shift = (L::cz[i] * p.ny + L::cy[i]) * p.nx + L::cx[i];
-            raw[i] = load_at(fin + ((long long)i * p.pitch - shift), cb);
-        }
-        __builtin_amdgcn_sched_barrier(0);
-    } else if (__all(inner_yz)) {
-#pragma unroll
-        for (int i = 0; i < L::Q; ++i) {
-            int src = cell - ((L::cz[i] * p.ny + L::cy[i]) * p.nx + L::cx[i]);
-            if (L::cx[i] > 0 && x < L::cx[i]) src += p.nx;
-            if (L::cx[i] < 0 && x >= p.nx + L::cx[i]) src -= p.nx;
-            raw[i] = load_at(fin + (long long)i * p.pitch, (unsigned)src * (unsigned)sizeof(T));
-        }
-        __builtin_amdgcn_sched_barrier(0);
-    } else {
-        int xs[7], ys[7], zs[7];
-#pragma unroll
-        for (int k = 0; k < 7; ++k) {
-            xs[k] = wrapc(x + k - 3, p.nx);
-            ys[k] = wrapc(y + k - 3, p.ny);
-            zs[k] = (L::D == 3) ? wrapc(z + k - 3, p.nz) : 0;
-        }
-#pragma unroll
-        for (int i = 0; i < L::Q; ++i) {
-            const int src = (zs[3 - L::cz[i]] * p.ny + ys[3 - L::cy[i]]) * p.nx + xs[3 - L::cx[i]];
-            raw[i] = load_at(fin + (long long)i * p.pitch, (unsigned)src * (unsigned)sizeof(T));
-        }
-        __builtin_amdgcn_sched_barrier(0);
-    }
-}
-
-// Store the post-collision populations of a node in a new frame fn (written
-// to the frame plane of fout): h_i(fn) = h_i(fo) + R_i(fo) - R_i(fn), one
-// shift per shell.
-template <class L, int ST>
+// Store the post-collision populations of a node.  FM_CELL: in a new frame
+// fn (written to the frame plane of fout), h_i(fn) = h_i(fo) + R_i(fo) -
+// R_i(fn), one shift per shell.  FM_PLANE: the frame of the plane is fixed,
+// the values are stored as they are.
+template <class L, int ST, int FM>
 __device__ __forceinline__ void store_cell(const KParams& p, typename Codec<ST>::T* __restrict__ fout, long long cell,
                                            float (&f)[L::Q], const Frame& fo, float rho, float thb)
 {
-    const uint32_t packed = pack_frame(rho, thb);
-    frame_plane<ST>(fout, p.pitch, L::Q)[cell] = packed;
-    const Frame fn = unpack_frame(packed);
-    const FrameRef<L> ref = frame_ref<L>(fo);
-    float sh[L::NS];  // R(fo) - R(fn)
+    if constexpr (FM == FM_CELL) {
+        const uint32_t packed = pack_frame(rho, thb);
+        frame_plane<ST>(fout, p.pitch, L::Q)[cell] = packed;
+        const Frame fn = unpack_frame(packed);
+        const FrameRef<L> ref = frame_ref<L>(fo);
+        float sh[L::NS];  // R(fo) - R(fn)
 #pragma unroll
-    for (int s = 0; s < L::NS; ++s) sh[s] = -frame_shift<L>(ref, s, fn);
+        for (int s = 0; s < L::NS; ++s) sh[s] = -frame_shift<L>(ref, s, fn);
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i)
-        fout[(long long)i * p.pitch + cell] = Codec<ST>::enc(f[i] + sh[L::shell[i]], p.dref[i]);
+        for (int i = 0; i < L::Q; ++i)
+            fout[(long long)i * p.pitch + cell] = Codec<ST>::enc(f[i] + sh[L::shell[i]], p.dref[i]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) fout[(long long)i * p.pitch + cell] = Codec<ST>::enc(f[i], p.dref[i]);
+    }
 }
 
 template <class L>
@@ -203,12 +189,12 @@ __device__ __forceinline__ void wall_coord(const KParams& p, int x, int y, int z
 // every pass over the state so that they agree bitwise.  f holds the
 // deviations h_i.  WALLS = false compiles out the wall closure (periodic
 // domains and interior planes).
-template <class L, int ST, bool WALLS>
+template <class L, int ST, bool WALLS, int FM>
 __device__ __forceinline__ void load_state(const KParams& p, const typename Codec<ST>::T* __restrict__ fin,
                                            const float* __restrict__ tgt_in, int x, int y, int z,
                                            float (&f)[L::Q], Frame& fo, float& dr, float (&j)[3], float& ed)
 {
-    uint64_t unk = pull_cell<L, ST, WALLS>(p, fin, x, y, z, f, fo);
+    uint64_t unk = pull_cell<L, ST, WALLS, FM>(p, fin, x, y, z, f, fo);
     if (WALLS && p.walls && unk) {
         int kw, nw, cil;
         wall_coord<L>(p, x, y, z, kw, nw, cil);
@@ -319,7 +305,7 @@ __device__ __forceinline__ float theta_field(const KParams& p, const Frame& fo, 
 
 // One full step of one cell: pull, closure, moments, sources, collision and
 // store of the post-collision populations at `cell` of fout.
-template <class L, int ST, int FAM, bool WALLS>
+template <class L, int ST, int FAM, bool WALLS, int FM>
 __device__ __forceinline__ void step_cell(const KParams& p, const typename Codec<ST>::T* __restrict__ fin,
                                           typename Codec<ST>::T* __restrict__ fout, const float* __restrict__ aux_f,
                                           const double* __restrict__ aux_d, const float* __restrict__ tgt_in,
@@ -330,7 +316,7 @@ __device__ __forceinline__ void step_cell(const KParams& p, const typename Codec
     cell_coords<L>(p, cell, x, y, z);
     float f[L::Q], dr, j[3], ed;
     Frame fo;
-    load_state<L, ST, WALLS>(p, fin, tgt_in, x, y, z, f, fo, dr, j, ed);
+    load_state<L, ST, WALLS, FM>(p, fin, tgt_in, x, y, z, f, fo, dr, j, ed);
     Macro m;
     float pc;
     full_macro<L, ST, FAM>(p, fo, aux_f, aux_d, x, y, z, dr, j, ed, m, pc);
@@ -342,12 +328,12 @@ __device__ __forceinline__ void step_cell(const KParams& p, const typename Codec
         hc = p.hfac * m.rho * m.theta;
     }
     collide<L>(p, fo, f, m, hc, gT, pc);
-    store_cell<L, ST>(p, fout, cell, f, fo, m.rho, m.thb);
+    store_cell<L, ST, FM>(p, fout, cell, f, fo, m.rho, m.thb);
 }
 
 // Field pass of one cell: theta (thermal family) or psi (pressure-tensor
 // family) of the current state, read by the stencil of the following pass.
-template <class L, int ST, int FAM, bool WALLS>
+template <class L, int ST, int FAM, bool WALLS, int FM>
 __device__ __forceinline__ void aux_cell(const KParams& p, const typename Codec<ST>::T* __restrict__ fin,
                                          const float* __restrict__ tgt_in, float* __restrict__ aux_f,
                                          double* __restrict__ aux_d, int cell)
@@ -356,7 +342,7 @@ __device__ __forceinline__ void aux_cell(const KParams& p, const typename Codec<
     cell_coords<L>(p, cell, x, y, z);
     float f[L::Q], dr, j[3], ed;
     Frame fo;
-    load_state<L, ST, WALLS>(p, fin, tgt_in, x, y, z, f, fo, dr, j, ed);
+    load_state<L, ST, WALLS, FM>(p, fin, tgt_in, x, y, z, f, fo, dr, j, ed);
     if (FAM == FAM_PTENSOR) {
         bool bad = false;
         aux_d[cell] = psi_vdw(p, (double)fo.rho + (double)dr, L::c0sq, bad);
@@ -383,7 +369,7 @@ __device__ __forceinline__ void init_frame_cell(const KParams& p, const float* _
 // Initial state of one cell: f^0_i(x) = f^eq_i(rho, u, theta)(x), written to
 // the slot x - c_i that the first pull of node x reads, in the frame of that
 // slot's cell.
-template <class L, int ST>
+template <class L, int ST, int FM>
 __device__ __forceinline__ void init_cell(const KParams& p, const float* __restrict__ rho,
                                           const float* __restrict__ u, const float* __restrict__ theta,
                                           typename Codec<ST>::T* __restrict__ fout, float* __restrict__ tgt, int cell)
@@ -402,8 +388,9 @@ __device__ __forceinline__ void init_cell(const KParams& p, const float* __restr
     if (!(m.theta > 0.0f) || !(m.theta < 3.0e38f)) raise_err(p, HOLB_ERR_THETA_BIT);
     if (p.walls) write_targets<L>(p, tgt, x, y, z, m);
     const uint32_t* fp = frame_plane<ST>(fout, p.pitch, L::Q);
-    const Frame fo = unpack_frame(fp[cell]);
-    const FrameRef<L> ref = frame_ref<L>(fo);
+    const int mz = L::D == 3 ? z : y;
+    const Frame fo = FM == FM_CELL ? unpack_frame(fp[cell]) : plane_frame_of(p, mz);
+    [[maybe_unused]] const FrameRef<L> ref = frame_ref<L>(fo);
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
         int dx = wrapc(x - L::cx[i], p.nx);
@@ -422,10 +409,15 @@ __device__ __forceinline__ void init_cell(const KParams& p, const float* __restr
         }
         if (!inside) continue;
         const int slot = (dz * p.ny + dy) * p.nx + dx;
-        const Frame fs = unpack_frame(fp[slot]);
         // in the node's own frame, then moved into the slot cell's frame
         const float fe = feq_dev<L>(fo, i, m.rho, m.u, m.thb);
-        const float h = fe - frame_shift<L>(ref, L::shell[i], fs);
+        float h;
+        if constexpr (FM == FM_CELL) {
+            h = fe - frame_shift<L>(ref, L::shell[i], unpack_frame(fp[slot]));
+        } else {
+            const int cm = L::D == 3 ? L::cz[i] : L::cy[i];
+            h = cm == 0 ? fe : fe - p.plane_shift[((long long)mz * 7 + cm + 3) * L::NS + L::shell[i]];
+        }
         fout[(long long)i * p.pitch + slot] = Codec<ST>::enc(h, p.dref[i]);
     }
 }

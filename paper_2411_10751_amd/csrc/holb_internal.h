@@ -13,7 +13,8 @@ struct LaunchCtx {
     int lattice;          // 0 D2Q37, 1 D3Q39
     int storage;          // Storage
     int family;           // Family
-    int variant;          // kernel variant (0 = generic)
+    int variant;          // kernel variant (block order of the generic kernels)
+    int frames;           // FrameMode
     KParams kp;
     const void* pop_in;   // current state (post-collision of the last step)
     void* pop_out;        // next state
@@ -49,6 +50,7 @@ void deviation_reference(int lattice, double rho, const double* u, double theta,
 
 // Velocity set in library order.
 int lattice_Q(int lattice);
+int lattice_NS(int lattice);  // number of velocity shells
 int lattice_D(int lattice);
 void lattice_table(int lattice, int* c, double* w, double* c0sq);
 

@@ -1,8 +1,10 @@
 // gfx950 kernels of the high-order lattice Boltzmann step and their launchers.
 //
 // Data layout: populations are structure-of-arrays, Q planes of `pitch`
-// elements (256-byte aligned), cell = x + nx * (y + ny * z), followed by the
-// plane of per-cell frames (binary16 pairs rho, theta).  The state buffer
+// elements (256-byte aligned), cell = x + nx * (y + ny * z).  16-bit storage
+// keeps a frame per cell (binary16 pair rho, theta - 1) in a plane after the
+// populations; FP32 storage uses fixed per-plane frames held in a small table
+// (FrameMode in holb_params.h).  The state buffer
 // holds the post-collision populations of the last step; a step pulls
 // f^_i(x) = buf[i][x - c_i] (streaming, left side of Eq. 4.4), applies the wall
 // closure, forms the shifted moments (Eq. 4.5), the sources and the collision,
@@ -17,11 +19,11 @@
 #include "holb_cell.h"
 #include "holb_device.h"
 #include "holb_internal.h"
-#include "holb_march.h"
 
 namespace holb {
 
 constexpr int GEN_BLOCK = 256;
+
 
 // --------------------------------------------------------------- kernels
 
@@ -34,13 +36,67 @@ k_init_frame(const KParams p, const float* __restrict__ rho, const float* __rest
     if (cell < p.N) init_frame_cell<L, ST>(p, rho, theta, fout, cell);
 }
 
-template <class L, int ST>
+template <class L, int ST, int FM>
 __global__ void __launch_bounds__(GEN_BLOCK)
 k_init(const KParams p, const float* __restrict__ rho, const float* __restrict__ u,
        const float* __restrict__ theta, typename Codec<ST>::T* __restrict__ fout, float* __restrict__ tgt)
 {
     const int cell = xcd_block() * GEN_BLOCK + threadIdx.x;
-    if (cell < p.N) init_cell<L, ST>(p, rho, u, theta, fout, tgt, cell);
+    if (cell < p.N) init_cell<L, ST, FM>(p, rho, u, theta, fout, tgt, cell);
+}
+
+// Per-plane frames (FM_PLANE): the mean density and temperature of each plane
+// along the last axis of the initial fields, FP64 sums; one block per plane.
+__global__ void __launch_bounds__(256)
+k_plane_frames(const KParams p, const float* __restrict__ rho, const float* __restrict__ theta,
+               float* __restrict__ frames)
+{
+    __shared__ double red[4][2];
+    const long long c0 = (long long)blockIdx.x * p.nlayer;
+    double sr = 0.0, st = 0.0;
+    for (int k = threadIdx.x; k < p.nlayer; k += 256) {
+        sr += (double)rho[c0 + k];
+        st += (double)theta[c0 + k];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        sr += __shfl_xor(sr, off, 64);
+        st += __shfl_xor(st, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6][0] = sr;
+        red[threadIdx.x >> 6][1] = st;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double r = ((red[0][0] + red[1][0]) + red[2][0]) + red[3][0];
+        const double t = ((red[0][1] + red[1][1]) + red[2][1]) + red[3][1];
+        frames[2 * blockIdx.x] = (float)(r / p.nlayer);
+        frames[2 * blockIdx.x + 1] = (p.flags & KF_ISO) ? 0.0f : (float)(t / p.nlayer - 1.0);
+    }
+}
+
+// Shift table of the per-plane frames: R_s(frame(m - c_m)) - R_s(frame(m)) for
+// every plane m, march-axis velocity c_m in [-3, 3] and shell s (zero where
+// plane m - c_m lies beyond a wall: those populations are rebuilt, not read).
+template <class L>
+__global__ void k_plane_shift(const KParams p, const float* __restrict__ frames, float* __restrict__ shifts)
+{
+    const int m = blockIdx.x, t = threadIdx.x;
+    if (t >= 7 * L::NS) return;
+    const int cm = t / L::NS - 3, s = t % L::NS;
+    const int nm = L::D == 3 ? p.nz : p.ny;
+    int src = m - cm;
+    float v = 0.0f;
+    const bool inside = src >= 0 && src < nm;
+    if (inside || !p.walls) {
+        src = wrapc(src, nm);
+        Frame O, S;
+        O.rho = frames[2 * m]; O.thb = frames[2 * m + 1];
+        S.rho = frames[2 * src]; S.thb = frames[2 * src + 1];
+        const FrameRef<L> ref = frame_ref<L>(O);
+        v = cm == 0 ? 0.0f : frame_shift<L>(ref, s, S);
+    }
+    shifts[((long long)m * 7 + (cm + 3)) * L::NS + s] = v;
 }
 
 // A set of planes along the last axis, [lo0, lo0 + n0) and [lo1, lo1 + n1):
@@ -56,17 +112,17 @@ __device__ __forceinline__ int plane_cell(const KParams& p, const PlaneSet& ps, 
     return plane * p.nlayer + r;
 }
 
-template <class L, int ST, int FAM, bool WALLS>
+template <class L, int ST, int FAM, bool WALLS, int FM>
 __global__ void __launch_bounds__(GEN_BLOCK)
 k_aux(const KParams p, const PlaneSet ps, const typename Codec<ST>::T* __restrict__ fin,
       const float* __restrict__ tgt_in, float* __restrict__ aux_f, double* __restrict__ aux_d, int remap)
 {
     const int c = xcd_block(remap) * GEN_BLOCK + threadIdx.x;
     if (c < (ps.n0 + ps.n1) * p.nlayer)
-        aux_cell<L, ST, FAM, WALLS>(p, fin, tgt_in, aux_f, aux_d, plane_cell(p, ps, c));
+        aux_cell<L, ST, FAM, WALLS, FM>(p, fin, tgt_in, aux_f, aux_d, plane_cell(p, ps, c));
 }
 
-template <class L, int ST, int FAM, bool WALLS>
+template <class L, int ST, int FAM, bool WALLS, int FM>
 __global__ void __launch_bounds__(GEN_BLOCK)
 k_step(const KParams p, const PlaneSet ps, const typename Codec<ST>::T* __restrict__ fin,
        typename Codec<ST>::T* __restrict__ fout, const float* __restrict__ aux_f, const double* __restrict__ aux_d,
@@ -74,10 +130,11 @@ k_step(const KParams p, const PlaneSet ps, const typename Codec<ST>::T* __restri
 {
     const int c = xcd_block(remap) * GEN_BLOCK + threadIdx.x;
     if (c < (ps.n0 + ps.n1) * p.nlayer)
-        step_cell<L, ST, FAM, WALLS>(p, fin, fout, aux_f, aux_d, tgt_in, tgt_out, plane_cell(p, ps, c));
+        step_cell<L, ST, FAM, WALLS, FM>(p, fin, fout, aux_f, aux_d, tgt_in, tgt_out,
+                                                       plane_cell(p, ps, c));
 }
 
-template <class L, int ST, int FAM, bool WALLS>
+template <class L, int ST, int FAM, bool WALLS, int FM>
 __global__ void __launch_bounds__(GEN_BLOCK)
 k_fields(const KParams p, const typename Codec<ST>::T* __restrict__ fin, const float* __restrict__ aux_f,
          const double* __restrict__ aux_d, const float* __restrict__ tgt_in, float* __restrict__ rho_out,
@@ -89,7 +146,7 @@ k_fields(const KParams p, const typename Codec<ST>::T* __restrict__ fin, const f
     cell_coords<L>(p, cell, x, y, z);
     float f[L::Q], dr, j[3], ed;
     Frame fo;
-    load_state<L, ST, WALLS>(p, fin, tgt_in, x, y, z, f, fo, dr, j, ed);
+    load_state<L, ST, WALLS, FM>(p, fin, tgt_in, x, y, z, f, fo, dr, j, ed);
     Macro m;
     float pc;
     full_macro<L, ST, FAM>(p, fo, aux_f, aux_d, x, y, z, dr, j, ed, m, pc);
@@ -110,7 +167,7 @@ __device__ __forceinline__ double wave_sum(double v)
 
 // Block partials of mass, momentum and energy in FP64 (wavefront shuffles,
 // then LDS across the block's waves).
-template <class L, int ST, int FAM, bool WALLS>
+template <class L, int ST, int FAM, bool WALLS, int FM>
 __global__ void __launch_bounds__(GEN_BLOCK)
 k_reduce(const KParams p, const typename Codec<ST>::T* __restrict__ fin, const float* __restrict__ aux_f,
          const double* __restrict__ aux_d, const float* __restrict__ tgt_in, double* __restrict__ partials)
@@ -123,7 +180,7 @@ k_reduce(const KParams p, const typename Codec<ST>::T* __restrict__ fin, const f
         cell_coords<L>(p, cell, x, y, z);
         float f[L::Q], dr, j[3], ed;
         Frame fo;
-        load_state<L, ST, WALLS>(p, fin, tgt_in, x, y, z, f, fo, dr, j, ed);
+        load_state<L, ST, WALLS, FM>(p, fin, tgt_in, x, y, z, f, fo, dr, j, ed);
         Macro m;
         float pc;
         full_macro<L, ST, FAM>(p, fo, aux_f, aux_d, x, y, z, dr, j, ed, m, pc);
@@ -174,13 +231,13 @@ __global__ void __launch_bounds__(256) k_reduce_final(const double* __restrict__
 
 static inline int nblocks_for(int N) { return (N + GEN_BLOCK - 1) / GEN_BLOCK; }
 
-template <class L, int ST, int FAM>
+template <class L, int ST, int FAM, int FM>
 struct Launch {
     using T = typename Codec<ST>::T;
 
     static int nm(const KParams& p) { return L::D == 3 ? p.nz : p.ny; }
-    // generic kernels: variant 0 cell order, 1 XCD-contiguous eighths, 2 plane
-    // bands per XCD (argument of xcd_block); >= 3: marching kernels
+    // variant 0 cell order, 1 XCD-contiguous eighths, 2 plane bands per XCD
+    // (argument of xcd_block)
     static int remap(const LaunchCtx& c)
     {
         if (c.variant == 1) return -1;
@@ -190,16 +247,25 @@ struct Launch {
         }
         return 0;
     }
-    static bool marching(const LaunchCtx& c) { return c.variant >= 3 && march_variant_supported(c, c.variant); }
     static PlaneSet all(const KParams& p) { return PlaneSet{0, nm(p), 0, 0}; }
 
     static hipError_t init(const LaunchCtx& c, const float* rho, const float* u, const float* th)
     {
-        hipLaunchKernelGGL((k_init_frame<L, ST>), dim3(nblocks_for(c.kp.N)), dim3(GEN_BLOCK), 0, c.stream, c.kp,
-                           rho, th, (T*)c.pop_out);
+        if constexpr (FM == FM_CELL) {
+            hipLaunchKernelGGL((k_init_frame<L, ST>), dim3(nblocks_for(c.kp.N)), dim3(GEN_BLOCK), 0, c.stream,
+                               c.kp, rho, th, (T*)c.pop_out);
+        } else {
+            const int n = nm(c.kp);
+            hipLaunchKernelGGL(k_plane_frames, dim3(n), dim3(256), 0, c.stream, c.kp, rho, th,
+                               (float*)c.kp.plane_frame);
+            hipError_t r = hipGetLastError();
+            if (r != hipSuccess) return r;
+            hipLaunchKernelGGL((k_plane_shift<L>), dim3(n), dim3(64), 0, c.stream, c.kp, c.kp.plane_frame,
+                               (float*)c.kp.plane_shift);
+        }
         hipError_t r = hipGetLastError();
         if (r != hipSuccess) return r;
-        hipLaunchKernelGGL((k_init<L, ST>), dim3(nblocks_for(c.kp.N)), dim3(GEN_BLOCK), 0, c.stream, c.kp, rho, u,
+        hipLaunchKernelGGL((k_init<L, ST, FM>), dim3(nblocks_for(c.kp.N)), dim3(GEN_BLOCK), 0, c.stream, c.kp, rho, u,
                            th, (T*)c.pop_out, (float*)c.tgt_out);
         return hipGetLastError();
     }
@@ -212,10 +278,10 @@ struct Launch {
         if (n == 0) return hipSuccess;
         const dim3 grid(nblocks_for(n));
         if (walls)
-            hipLaunchKernelGGL((k_aux<L, ST, FAM, true>), grid, dim3(GEN_BLOCK), 0, c.stream, c.kp, ps,
+            hipLaunchKernelGGL((k_aux<L, ST, FAM, true, FM>), grid, dim3(GEN_BLOCK), 0, c.stream, c.kp, ps,
                                (const T*)c.pop_in, c.tgt_in, c.aux_f, c.aux_d, remap(c));
         else
-            hipLaunchKernelGGL((k_aux<L, ST, FAM, false>), grid, dim3(GEN_BLOCK), 0, c.stream, c.kp, ps,
+            hipLaunchKernelGGL((k_aux<L, ST, FAM, false, FM>), grid, dim3(GEN_BLOCK), 0, c.stream, c.kp, ps,
                                (const T*)c.pop_in, c.tgt_in, c.aux_f, c.aux_d, remap(c));
         return hipGetLastError();
     }
@@ -226,10 +292,10 @@ struct Launch {
         if (n == 0) return hipSuccess;
         const dim3 grid(nblocks_for(n));
         if (walls)
-            hipLaunchKernelGGL((k_step<L, ST, FAM, true>), grid, dim3(GEN_BLOCK), 0, c.stream, c.kp, ps,
+            hipLaunchKernelGGL((k_step<L, ST, FAM, true, FM>), grid, dim3(GEN_BLOCK), 0, c.stream, c.kp, ps,
                                (const T*)c.pop_in, (T*)c.pop_out, c.aux_f, c.aux_d, c.tgt_in, c.tgt_out, remap(c));
         else
-            hipLaunchKernelGGL((k_step<L, ST, FAM, false>), grid, dim3(GEN_BLOCK), 0, c.stream, c.kp, ps,
+            hipLaunchKernelGGL((k_step<L, ST, FAM, false, FM>), grid, dim3(GEN_BLOCK), 0, c.stream, c.kp, ps,
                                (const T*)c.pop_in, (T*)c.pop_out, c.aux_f, c.aux_d, c.tgt_in, c.tgt_out, remap(c));
         return hipGetLastError();
     }
@@ -263,18 +329,6 @@ struct Launch {
 
     static hipError_t step(const LaunchCtx& c)
     {
-        const int n = nm(c.kp);
-        if (marching(c)) {
-            if (!c.kp.walls) return timed(c, [&] { return march_step<L, ST, FAM>(c, 0, n); });
-            // wall layers by the generic kernels: theta of the four planes
-            // next to each wall, then the collision of the three wall
-            // layers; the march takes the planes between them and reads the
-            // theta of its two edge planes from the field
-            hipError_t r = aux_planes(c, PlaneSet{0, 4, n - 4, 4}, true);
-            if (r == hipSuccess) r = step_planes(c, wall_layers(c.kp), true);
-            if (r == hipSuccess) r = timed(c, [&] { return march_step<L, ST, FAM>(c, 3, n - 3); });
-            return r;
-        }
         hipError_t r = aux(c);
         if (r != hipSuccess) return r;
         if (!c.kp.walls) return timed(c, [&] { return step_planes(c, all(c.kp), false); });
@@ -286,13 +340,10 @@ struct Launch {
     static void dominant(const LaunchCtx& c, char* name, size_t len, long long* cells)
     {
         const int n = nm(c.kp);
-        const bool march = marching(c);
         const int planes = c.kp.walls ? n - 6 : n;
         if (cells) *cells = (long long)planes * c.kp.nlayer;
         if (!name || !len) return;
-        const char* lat = L::D == 3 ? "D3Q39" : "D2Q37";
-        if (march) march_kernel_name<L>(c.variant - 2, lat, ST, name, len);
-        else snprintf(name, len, "k_step<%s,%d,%d,false>", lat, ST, FAM);
+        snprintf(name, len, "k_step<%s,%d,%d,false,%d>", L::D == 3 ? "D3Q39" : "D2Q37", ST, FAM, FM);
     }
 
     static hipError_t fields(const LaunchCtx& c, float* rho, float* u, float* th)
@@ -302,10 +353,10 @@ struct Launch {
             if (r != hipSuccess) return r;
         }
         if (c.kp.walls)
-            hipLaunchKernelGGL((k_fields<L, ST, FAM, true>), dim3(nblocks_for(c.kp.N)), dim3(GEN_BLOCK), 0,
+            hipLaunchKernelGGL((k_fields<L, ST, FAM, true, FM>), dim3(nblocks_for(c.kp.N)), dim3(GEN_BLOCK), 0,
                                c.stream, c.kp, (const T*)c.pop_in, c.aux_f, c.aux_d, c.tgt_in, rho, u, th);
         else
-            hipLaunchKernelGGL((k_fields<L, ST, FAM, false>), dim3(nblocks_for(c.kp.N)), dim3(GEN_BLOCK), 0,
+            hipLaunchKernelGGL((k_fields<L, ST, FAM, false, FM>), dim3(nblocks_for(c.kp.N)), dim3(GEN_BLOCK), 0,
                                c.stream, c.kp, (const T*)c.pop_in, c.aux_f, c.aux_d, c.tgt_in, rho, u, th);
         return hipGetLastError();
     }
@@ -319,10 +370,10 @@ struct Launch {
         const int nb = nblocks_for(c.kp.N);
         if (nb > c.max_partials) return hipErrorInvalidValue;
         if (c.kp.walls)
-            hipLaunchKernelGGL((k_reduce<L, ST, FAM, true>), dim3(nb), dim3(GEN_BLOCK), 0, c.stream, c.kp,
+            hipLaunchKernelGGL((k_reduce<L, ST, FAM, true, FM>), dim3(nb), dim3(GEN_BLOCK), 0, c.stream, c.kp,
                                (const T*)c.pop_in, c.aux_f, c.aux_d, c.tgt_in, c.partials);
         else
-            hipLaunchKernelGGL((k_reduce<L, ST, FAM, false>), dim3(nb), dim3(GEN_BLOCK), 0, c.stream, c.kp,
+            hipLaunchKernelGGL((k_reduce<L, ST, FAM, false, FM>), dim3(nb), dim3(GEN_BLOCK), 0, c.stream, c.kp,
                                (const T*)c.pop_in, c.aux_f, c.aux_d, c.tgt_in, c.partials);
         hipError_t r = hipGetLastError();
         if (r != hipSuccess) return r;
@@ -331,17 +382,17 @@ struct Launch {
     }
 };
 
-template <class L, int ST>
+template <class L, int ST, int FM>
 static hipError_t dispatch_family(const LaunchCtx& c, int op, const float* a, const float* b, const float* d,
                                   float* o1, float* o2, float* o3, double* dout)
 {
-#define HOLB_OPS(FAM)                                              \
-    switch (op) {                                                  \
-    case 0: return Launch<L, ST, FAM>::init(c, a, b, d);           \
-    case 1: return Launch<L, ST, FAM>::step(c);                    \
-    case 2: return Launch<L, ST, FAM>::aux(c);                     \
-    case 3: return Launch<L, ST, FAM>::fields(c, o1, o2, o3);      \
-    case 4: return Launch<L, ST, FAM>::reduce(c, dout);            \
+#define HOLB_OPS(FAM)                                                  \
+    switch (op) {                                                      \
+    case 0: return Launch<L, ST, FAM, FM>::init(c, a, b, d);           \
+    case 1: return Launch<L, ST, FAM, FM>::step(c);                    \
+    case 2: return Launch<L, ST, FAM, FM>::aux(c);                     \
+    case 3: return Launch<L, ST, FAM, FM>::fields(c, o1, o2, o3);      \
+    case 4: return Launch<L, ST, FAM, FM>::reduce(c, dout);            \
     }
     switch (c.family) {
     case FAM_LOCAL: HOLB_OPS(FAM_LOCAL) break;
@@ -357,9 +408,12 @@ static hipError_t dispatch_storage(const LaunchCtx& c, int op, const float* a, c
                                    float* o1, float* o2, float* o3, double* dout)
 {
     switch (c.storage) {
-    case ST_F32: return dispatch_family<L, ST_F32>(c, op, a, b, d, o1, o2, o3, dout);
-    case ST_F16: return dispatch_family<L, ST_F16>(c, op, a, b, d, o1, o2, o3, dout);
-    case ST_BF16: return dispatch_family<L, ST_BF16>(c, op, a, b, d, o1, o2, o3, dout);
+    // per-plane frames are FP32 only (validated on the host)
+    case ST_F32:
+        if (c.frames == FM_PLANE) return dispatch_family<L, ST_F32, FM_PLANE>(c, op, a, b, d, o1, o2, o3, dout);
+        return dispatch_family<L, ST_F32, FM_CELL>(c, op, a, b, d, o1, o2, o3, dout);
+    case ST_F16: return dispatch_family<L, ST_F16, FM_CELL>(c, op, a, b, d, o1, o2, o3, dout);
+    case ST_BF16: return dispatch_family<L, ST_BF16, FM_CELL>(c, op, a, b, d, o1, o2, o3, dout);
     }
     return hipErrorInvalidValue;
 }
@@ -392,11 +446,16 @@ int reduce_blocks(const LaunchCtx& c) { return nblocks_for(c.kp.N); }
 template <class L, int ST>
 static void dominant_family(const LaunchCtx& c, char* name, size_t len, long long* cells)
 {
+    long long n = 0;
     switch (c.family) {
-    case FAM_LOCAL: Launch<L, ST, FAM_LOCAL>::dominant(c, name, len, cells); break;
-    case FAM_THERMAL: Launch<L, ST, FAM_THERMAL>::dominant(c, name, len, cells); break;
-    default: Launch<L, ST, FAM_PTENSOR>::dominant(c, name, len, cells); break;
+    case FAM_LOCAL: Launch<L, ST, FAM_LOCAL, FM_CELL>::dominant(c, nullptr, 0, &n); break;
+    case FAM_THERMAL: Launch<L, ST, FAM_THERMAL, FM_CELL>::dominant(c, nullptr, 0, &n); break;
+    default: Launch<L, ST, FAM_PTENSOR, FM_CELL>::dominant(c, nullptr, 0, &n); break;
     }
+    if (cells) *cells = n;
+    // kernel template arguments as a profiler lists them
+    if (name && len)
+        snprintf(name, len, "k_step<%s,%d,%d,false,%d>", L::D == 3 ? "D3Q39" : "D2Q37", ST, c.family, c.frames);
 }
 
 template <class L>
@@ -415,13 +474,9 @@ void dominant_kernel(const LaunchCtx& c, char* name, size_t len, long long* cell
     else dominant_storage<D3Q39>(c, name, len, cells);
 }
 
-int num_variants(const LaunchCtx& c) { return 3 + march_num_variants(c); }
+int num_variants(const LaunchCtx&) { return 3; }
 
-bool variant_supported(const LaunchCtx& c, int variant)
-{
-    if (variant >= 0 && variant <= 2) return true;
-    return march_variant_supported(c, variant);
-}
+bool variant_supported(const LaunchCtx&, int variant) { return variant >= 0 && variant <= 2; }
 
 // ------------------------------------------------------- host-side tables
 
@@ -440,6 +495,7 @@ static void table_of(int* c, double* w, double* c0sq)
 }
 
 int lattice_Q(int lattice) { return lattice == 0 ? D2Q37::Q : D3Q39::Q; }
+int lattice_NS(int lattice) { return lattice == 0 ? D2Q37::NS : D3Q39::NS; }
 int lattice_D(int lattice) { return lattice == 0 ? D2Q37::D : D3Q39::D; }
 void lattice_table(int lattice, int* c, double* w, double* c0sq)
 {

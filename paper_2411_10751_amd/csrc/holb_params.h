@@ -13,6 +13,11 @@ enum Family { FAM_LOCAL = 0, FAM_THERMAL = 1, FAM_PTENSOR = 2 };
 
 enum : unsigned { KF_BODY = 1u, KF_ISO = 2u };
 
+// How stored populations are referenced (see the frame section of
+// holb_device.h): a frame per cell, kept beside the populations, or a fixed
+// frame per plane along the last axis, kept in a small table.
+enum FrameMode { FM_CELL = 0, FM_PLANE = 1 };
+
 enum : unsigned { HOLB_ERR_DENSITY_BIT = 1u, HOLB_ERR_THETA_BIT = 2u, HOLB_ERR_EOS_BIT = 4u };
 
 constexpr int QMAX = 39;
@@ -60,6 +65,11 @@ struct KParams {
     float thb_ref;       //   are handled as h_i = f_i / w_i - f^eq_i(rho0, 0, theta0) / w_i
     float dref[QMAX];    // d_i = (f^eq_i(rho0, u0, theta0) - f^eq_i(rho0, 0, theta0)) / w_i (16-bit offset)
     unsigned* err;       // device error word
+    // FM_PLANE: rho and theta - 1 of each plane along the last axis (2 floats
+    // per plane), and the shifts R_s(frame(m - c_m)) - R_s(frame(m)) at
+    // [(m * 7 + c_m + 3) * NS + s] for plane m, march-axis velocity c_m, shell s
+    const float* plane_frame;
+    const float* plane_shift;
 };
 
 // Wall targets: 6 layers (3 per wall) x nlayer cells x (D + 2) floats, laid

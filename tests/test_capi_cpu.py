@@ -70,6 +70,8 @@ def _cfg(**kw):
     (dict(walls=1, ny=6), holb.EINVAL),
     (dict(g=(float("inf"), 0, 0)), holb.EINVAL),
     (dict(lattice=1, nx=1024, ny=1024, nz=1024), holb.ESIZE),
+    (dict(frames=3), holb.EINVAL),
+    (dict(storage=1, rho0=1.0, frames=2), holb.EUNSUPPORTED),
 ])
 def test_config_errors(bad, code):
     with pytest.raises(holb.HolbError) as ei:
@@ -115,7 +117,8 @@ def test_create_is_host_only_and_checks_workspace():
     assert holb.holb_set_variant(h, 10 ** 6) == holb.EUNSUPPORTED
     sb = ctypes.c_size_t()
     assert holb.holb_state_bytes(h, ctypes.byref(sb)) == holb.OK
-    assert sb.value == 37 * 1024 * 4 + 1024 * 4  # Q planes + one frame (2 x binary16) per cell
+    # Q planes + one frame (2 x binary16) per cell (periodic FP32: per-cell frames)
+    assert sb.value == 37 * 1024 * 4 + 1024 * 4
     assert holb.holb_get_state(h, ctypes.c_void_p(fake), sb.value - 4) == holb.ESIZE
     assert holb.holb_destroy(h) == holb.OK
 

@@ -122,10 +122,12 @@ def _rb_small():
     return _rb(24, 20, 60)
 
 
-def test_rb3d_walls_fp32():
+@pytest.mark.parametrize("frames", [0, 1])
+def test_rb3d_walls_fp32(frames):
     w = _rb_small()
+    w["config"]["frames"] = frames
     g, o = _both(w)
-    assert_parity(g, o, 1, TOL[0], w["name"])
+    assert_parity(g, o, 1, TOL[0], w["name"] + " frames %d" % frames)
 
 
 _RB_MID = {}
@@ -161,10 +163,29 @@ def test_rb3d_walls_16bit(storage):
 
 
 def test_periodic_3d_thermal_body():
+    """Periodic D3Q39 box started from the Rayleigh-Benard ramp, which jumps
+    by 0.4 in theta across the periodic boundary (default frames: per cell)."""
     w = _rb(20, 16, 50, walls=0)
     w["config"]["g"] = (1e-4, -2e-4, 3e-4)
     g, o = _both(w)
     assert_parity(g, o, 1, TOL[0], "periodic 3D 20x20x16")
+
+
+@pytest.mark.parametrize("frames", [0, 2])
+def test_periodic_3d_smooth(frames):
+    """Periodic D3Q39 box with a smooth periodic temperature profile (theta =
+    1.2 + 0.2 sin(2 pi z / nz) + noise, rho = 1.2 / theta), thermal + body
+    force; default (per-cell) and per-plane frames."""
+    rng = np.random.default_rng(11)
+    n, nz = 20, 24
+    z = np.arange(nz)[:, None, None] * np.ones((1, n, n))
+    th = 1.2 + 0.2 * np.sin(2 * np.pi * z / nz) + 1e-3 * rng.standard_normal((nz, n, n))
+    cfg = inputs.base_config(lattice=1, nx=n, ny=n, nz=nz, tau_hat=0.56, sources=inputs.SRC_BODY | inputs.SRC_THERMAL,
+                             g=(1e-4, -2e-4, 3e-4), prandtl=0.71, theta0=1.2, frames=frames)
+    w = dict(name="periodic_smooth", config=cfg, rho=(1.2 / th).astype(np.float32),
+             u=np.zeros((3, nz, n, n), np.float32), theta=th.astype(np.float32), steps=60)
+    g, o = _both(w)
+    assert_parity(g, o, 1, TOL[0], "periodic 3D smooth 20x20x24 frames %d" % frames)
 
 
 def test_2d_walls_couette_like():
@@ -385,7 +406,8 @@ def test_batched_parity_and_self_consistency():
         o = run_oracle(r["config"], r["rho"], r["u"], r["theta"], 60)
         assert_parity(gf, o, 0, TOL[0], r["name"])
         if k < 3:
-            alone = run_gpu(r["config"], r["rho"], r["u"], r["theta"], 60)
+            # batched runs keep per-plane frames: the same run alone, same frames
+            alone = run_gpu(dict(r["config"], frames=2), r["rho"], r["u"], r["theta"], 60)
             for a, bb in zip(gf, alone):
                 assert np.array_equal(a, bb)
     torch.cuda.synchronize()

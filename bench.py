@@ -281,6 +281,9 @@ def main():
             "walls": cfg["walls"],
             "storage": args.storage,
             "variant": variant,
+            # frames as the library resolves them (auto: per plane for FP32 with walls)
+            "frames": {1: "cell", 2: "plane"}.get(cfg.get("frames", 0),
+                                                  "plane" if storage == 0 and cfg.get("walls") else "cell"),
             "mass": totals[0],
         },
         "roofline": {

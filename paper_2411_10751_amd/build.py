@@ -11,7 +11,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libholb.so")
-SOURCES = ["holb_kernels.hip", "holb_capi.hip", "holb_batch.hip"]
+SOURCES = ["holb_inst_d3_f32.hip", "holb_inst_d3_16.hip", "holb_inst_d2_f32.hip", "holb_inst_d2_16.hip",
+           "holb_kernels.hip", "holb_capi.hip", "holb_batch.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
@@ -33,7 +34,7 @@ def hipcc():
     return h
 
 
-def build(verbose=False, jobs=4):
+def build(verbose=False, jobs=7):
     """Compile every source and link the shared library; always rebuilds."""
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)

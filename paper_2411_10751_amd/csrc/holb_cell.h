@@ -327,7 +327,7 @@ __device__ __forceinline__ void step_cell(const KParams& p, const typename Codec
         grad_theta<L>(p, aux_f, x, y, z, gT);
         hc = p.hfac * m.rho * m.theta;
     }
-    collide<L>(p, fo, f, m, hc, gT, pc);
+    collide<L, ST == ST_F32>(p, fo, f, m, hc, gT, pc);
     store_cell<L, ST, FM>(p, fout, cell, f, fo, m.rho, m.thb);
 }
 

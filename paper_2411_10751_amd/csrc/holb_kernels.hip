@@ -1,429 +1,21 @@
-// gfx950 kernels of the high-order lattice Boltzmann step and their launchers.
-//
-// Data layout: populations are structure-of-arrays, Q planes of `pitch`
-// elements (256-byte aligned), cell = x + nx * (y + ny * z).  16-bit storage
-// keeps a frame per cell (binary16 pair rho, theta - 1) in a plane after the
-// populations; FP32 storage uses fixed per-plane frames held in a small table
-// (FrameMode in holb_params.h).  The state buffer
-// holds the post-collision populations of the last step; a step pulls
-// f^_i(x) = buf[i][x - c_i] (streaming, left side of Eq. 4.4), applies the wall
-// closure, forms the shifted moments (Eq. 4.5), the sources and the collision,
-// and writes the post-collision populations of x into the other buffer.
-//
-// Generic variant: one cell per thread, 256-thread blocks along x.  Stencil
-// sources (temperature gradient, pseudopotential force) read a field written
-// by a preceding pass over the same state (launch_aux).
+// Host side of the kernel launchers: dispatch to the instantiation units,
+// dominant-kernel bookkeeping, lattice tables and the 16-bit offset.
 #include <hip/hip_runtime.h>
 #include <stdio.h>
 
-#include "holb_cell.h"
-#include "holb_device.h"
-#include "holb_internal.h"
+#include "holb_kernels.h"
 
 namespace holb {
-
-constexpr int GEN_BLOCK = 256;
-
-
-// --------------------------------------------------------------- kernels
-
-template <class L, int ST>
-__global__ void __launch_bounds__(GEN_BLOCK)
-k_init_frame(const KParams p, const float* __restrict__ rho, const float* __restrict__ theta,
-             typename Codec<ST>::T* __restrict__ fout)
-{
-    const int cell = xcd_block() * GEN_BLOCK + threadIdx.x;
-    if (cell < p.N) init_frame_cell<L, ST>(p, rho, theta, fout, cell);
-}
-
-template <class L, int ST, int FM>
-__global__ void __launch_bounds__(GEN_BLOCK)
-k_init(const KParams p, const float* __restrict__ rho, const float* __restrict__ u,
-       const float* __restrict__ theta, typename Codec<ST>::T* __restrict__ fout, float* __restrict__ tgt)
-{
-    const int cell = xcd_block() * GEN_BLOCK + threadIdx.x;
-    if (cell < p.N) init_cell<L, ST, FM>(p, rho, u, theta, fout, tgt, cell);
-}
-
-// Per-plane frames (FM_PLANE): the mean density and temperature of each plane
-// along the last axis of the initial fields, FP64 sums; one block per plane.
-__global__ void __launch_bounds__(256)
-k_plane_frames(const KParams p, const float* __restrict__ rho, const float* __restrict__ theta,
-               float* __restrict__ frames)
-{
-    __shared__ double red[4][2];
-    const long long c0 = (long long)blockIdx.x * p.nlayer;
-    double sr = 0.0, st = 0.0;
-    for (int k = threadIdx.x; k < p.nlayer; k += 256) {
-        sr += (double)rho[c0 + k];
-        st += (double)theta[c0 + k];
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        sr += __shfl_xor(sr, off, 64);
-        st += __shfl_xor(st, off, 64);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        red[threadIdx.x >> 6][0] = sr;
-        red[threadIdx.x >> 6][1] = st;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const double r = ((red[0][0] + red[1][0]) + red[2][0]) + red[3][0];
-        const double t = ((red[0][1] + red[1][1]) + red[2][1]) + red[3][1];
-        frames[2 * blockIdx.x] = (float)(r / p.nlayer);
-        frames[2 * blockIdx.x + 1] = (p.flags & KF_ISO) ? 0.0f : (float)(t / p.nlayer - 1.0);
-    }
-}
-
-// Shift table of the per-plane frames: R_s(frame(m - c_m)) - R_s(frame(m)) for
-// every plane m, march-axis velocity c_m in [-3, 3] and shell s (zero where
-// plane m - c_m lies beyond a wall: those populations are rebuilt, not read).
-template <class L>
-__global__ void k_plane_shift(const KParams p, const float* __restrict__ frames, float* __restrict__ shifts)
-{
-    const int m = blockIdx.x, t = threadIdx.x;
-    if (t >= 7 * L::NS) return;
-    const int cm = t / L::NS - 3, s = t % L::NS;
-    const int nm = L::D == 3 ? p.nz : p.ny;
-    int src = m - cm;
-    float v = 0.0f;
-    const bool inside = src >= 0 && src < nm;
-    if (inside || !p.walls) {
-        src = wrapc(src, nm);
-        Frame O, S;
-        O.rho = frames[2 * m]; O.thb = frames[2 * m + 1];
-        S.rho = frames[2 * src]; S.thb = frames[2 * src + 1];
-        const FrameRef<L> ref = frame_ref<L>(O);
-        v = cm == 0 ? 0.0f : frame_shift<L>(ref, s, S);
-    }
-    shifts[((long long)m * 7 + (cm + 3)) * L::NS + s] = v;
-}
-
-// A set of planes along the last axis, [lo0, lo0 + n0) and [lo1, lo1 + n1):
-// the whole domain, or the layers next to the walls.
-struct PlaneSet {
-    int lo0, n0, lo1, n1;
-};
-
-__device__ __forceinline__ int plane_cell(const KParams& p, const PlaneSet& ps, int c)
-{
-    const int k = (int)fastdiv((unsigned)c, p.div_layer), r = c - k * p.nlayer;
-    const int plane = k < ps.n0 ? ps.lo0 + k : ps.lo1 + (k - ps.n0);
-    return plane * p.nlayer + r;
-}
-
-template <class L, int ST, int FAM, bool WALLS, int FM>
-__global__ void __launch_bounds__(GEN_BLOCK)
-k_aux(const KParams p, const PlaneSet ps, const typename Codec<ST>::T* __restrict__ fin,
-      const float* __restrict__ tgt_in, float* __restrict__ aux_f, double* __restrict__ aux_d, int remap)
-{
-    const int c = xcd_block(remap) * GEN_BLOCK + threadIdx.x;
-    if (c < (ps.n0 + ps.n1) * p.nlayer)
-        aux_cell<L, ST, FAM, WALLS, FM>(p, fin, tgt_in, aux_f, aux_d, plane_cell(p, ps, c));
-}
-
-template <class L, int ST, int FAM, bool WALLS, int FM>
-__global__ void __launch_bounds__(GEN_BLOCK)
-k_step(const KParams p, const PlaneSet ps, const typename Codec<ST>::T* __restrict__ fin,
-       typename Codec<ST>::T* __restrict__ fout, const float* __restrict__ aux_f, const double* __restrict__ aux_d,
-       const float* __restrict__ tgt_in, float* __restrict__ tgt_out, int remap)
-{
-    const int c = xcd_block(remap) * GEN_BLOCK + threadIdx.x;
-    if (c < (ps.n0 + ps.n1) * p.nlayer)
-        step_cell<L, ST, FAM, WALLS, FM>(p, fin, fout, aux_f, aux_d, tgt_in, tgt_out,
-                                                       plane_cell(p, ps, c));
-}
-
-template <class L, int ST, int FAM, bool WALLS, int FM>
-__global__ void __launch_bounds__(GEN_BLOCK)
-k_fields(const KParams p, const typename Codec<ST>::T* __restrict__ fin, const float* __restrict__ aux_f,
-         const double* __restrict__ aux_d, const float* __restrict__ tgt_in, float* __restrict__ rho_out,
-         float* __restrict__ u_out, float* __restrict__ th_out)
-{
-    const int cell = xcd_block() * GEN_BLOCK + threadIdx.x;
-    if (cell >= p.N) return;
-    int x, y, z;
-    cell_coords<L>(p, cell, x, y, z);
-    float f[L::Q], dr, j[3], ed;
-    Frame fo;
-    load_state<L, ST, WALLS, FM>(p, fin, tgt_in, x, y, z, f, fo, dr, j, ed);
-    Macro m;
-    float pc;
-    full_macro<L, ST, FAM>(p, fo, aux_f, aux_d, x, y, z, dr, j, ed, m, pc);
-    if (rho_out) rho_out[cell] = m.rho;
-    if (u_out) {
-#pragma unroll
-        for (int a = 0; a < L::D; ++a) u_out[(long long)a * p.N + cell] = m.u[a];
-    }
-    if (th_out) th_out[cell] = m.theta;
-}
-
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// Block partials of mass, momentum and energy in FP64 (wavefront shuffles,
-// then LDS across the block's waves).
-template <class L, int ST, int FAM, bool WALLS, int FM>
-__global__ void __launch_bounds__(GEN_BLOCK)
-k_reduce(const KParams p, const typename Codec<ST>::T* __restrict__ fin, const float* __restrict__ aux_f,
-         const double* __restrict__ aux_d, const float* __restrict__ tgt_in, double* __restrict__ partials)
-{
-    __shared__ double red[GEN_BLOCK / 64][5];
-    const int cell = blockIdx.x * GEN_BLOCK + threadIdx.x;
-    double v[5] = {0, 0, 0, 0, 0};
-    if (cell < p.N) {
-        int x, y, z;
-        cell_coords<L>(p, cell, x, y, z);
-        float f[L::Q], dr, j[3], ed;
-        Frame fo;
-        load_state<L, ST, WALLS, FM>(p, fin, tgt_in, x, y, z, f, fo, dr, j, ed);
-        Macro m;
-        float pc;
-        full_macro<L, ST, FAM>(p, fo, aux_f, aux_d, x, y, z, dr, j, ed, m, pc);
-        // mass from the frame and the deviation moment, in FP64
-        const double r = (double)fo.rho + (double)m.dr;
-        v[0] = r;
-        v[1] = r * (double)m.u[0];
-        v[2] = r * (double)m.u[1];
-        v[3] = r * (double)m.u[2];
-        const double uu = (double)m.u[0] * m.u[0] + (double)m.u[1] * m.u[1] + (double)m.u[2] * m.u[2];
-        v[4] = 0.5 * (r * uu + r * (L::D * L::c0sq) * ((1.0 + (double)fo.thb) + (double)m.dth));
-    }
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-        double s = wave_sum(v[k]);
-        if (lane == 0) red[wv][k] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x < 5) {
-        double s = 0.0;
-        for (int w = 0; w < GEN_BLOCK / 64; ++w) s += red[w][threadIdx.x];
-        partials[(long long)blockIdx.x * 5 + threadIdx.x] = s;
-    }
-}
-
-// Deterministic second pass: fixed strided order, then a fixed tree.
-__global__ void __launch_bounds__(256) k_reduce_final(const double* __restrict__ partials, int nblocks,
-                                                      double* __restrict__ out)
-{
-    __shared__ double red[4][5];
-    double v[5] = {0, 0, 0, 0, 0};
-    for (int b = threadIdx.x; b < nblocks; b += 256)
-#pragma unroll
-        for (int k = 0; k < 5; ++k) v[k] += partials[(long long)b * 5 + k];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-        double s = wave_sum(v[k]);
-        if (lane == 0) red[wv][k] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x < 5) out[threadIdx.x] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) +
-                                           red[3][threadIdx.x];
-}
-
-// -------------------------------------------------------------- launchers
-
-static inline int nblocks_for(int N) { return (N + GEN_BLOCK - 1) / GEN_BLOCK; }
-
-template <class L, int ST, int FAM, int FM>
-struct Launch {
-    using T = typename Codec<ST>::T;
-
-    static int nm(const KParams& p) { return L::D == 3 ? p.nz : p.ny; }
-    // variant 0 cell order, 1 XCD-contiguous eighths, 2 plane bands per XCD
-    // (argument of xcd_block)
-    static int remap(const LaunchCtx& c)
-    {
-        if (c.variant == 1) return -1;
-        if (c.variant == 2) {
-            const int bpp = c.kp.nlayer / GEN_BLOCK;  // blocks per plane
-            return (c.kp.nlayer % GEN_BLOCK == 0 && bpp % 8 == 0) ? bpp / 8 : 0;
-        }
-        return 0;
-    }
-    static PlaneSet all(const KParams& p) { return PlaneSet{0, nm(p), 0, 0}; }
-
-    static hipError_t init(const LaunchCtx& c, const float* rho, const float* u, const float* th)
-    {
-        if constexpr (FM == FM_CELL) {
-            hipLaunchKernelGGL((k_init_frame<L, ST>), dim3(nblocks_for(c.kp.N)), dim3(GEN_BLOCK), 0, c.stream,
-                               c.kp, rho, th, (T*)c.pop_out);
-        } else {
-            const int n = nm(c.kp);
-            hipLaunchKernelGGL(k_plane_frames, dim3(n), dim3(256), 0, c.stream, c.kp, rho, th,
-                               (float*)c.kp.plane_frame);
-            hipError_t r = hipGetLastError();
-            if (r != hipSuccess) return r;
-            hipLaunchKernelGGL((k_plane_shift<L>), dim3(n), dim3(64), 0, c.stream, c.kp, c.kp.plane_frame,
-                               (float*)c.kp.plane_shift);
-        }
-        hipError_t r = hipGetLastError();
-        if (r != hipSuccess) return r;
-        hipLaunchKernelGGL((k_init<L, ST, FM>), dim3(nblocks_for(c.kp.N)), dim3(GEN_BLOCK), 0, c.stream, c.kp, rho, u,
-                           th, (T*)c.pop_out, (float*)c.tgt_out);
-        return hipGetLastError();
-    }
-
-    // walls: the planes need the TMS closure (a wall layer of a walled domain)
-    static hipError_t aux_planes(const LaunchCtx& c, const PlaneSet& ps, bool walls)
-    {
-        if (FAM == FAM_LOCAL) return hipSuccess;
-        const int n = (ps.n0 + ps.n1) * c.kp.nlayer;
-        if (n == 0) return hipSuccess;
-        const dim3 grid(nblocks_for(n));
-        if (walls)
-            hipLaunchKernelGGL((k_aux<L, ST, FAM, true, FM>), grid, dim3(GEN_BLOCK), 0, c.stream, c.kp, ps,
-                               (const T*)c.pop_in, c.tgt_in, c.aux_f, c.aux_d, remap(c));
-        else
-            hipLaunchKernelGGL((k_aux<L, ST, FAM, false, FM>), grid, dim3(GEN_BLOCK), 0, c.stream, c.kp, ps,
-                               (const T*)c.pop_in, c.tgt_in, c.aux_f, c.aux_d, remap(c));
-        return hipGetLastError();
-    }
-
-    static hipError_t step_planes(const LaunchCtx& c, const PlaneSet& ps, bool walls)
-    {
-        const int n = (ps.n0 + ps.n1) * c.kp.nlayer;
-        if (n == 0) return hipSuccess;
-        const dim3 grid(nblocks_for(n));
-        if (walls)
-            hipLaunchKernelGGL((k_step<L, ST, FAM, true, FM>), grid, dim3(GEN_BLOCK), 0, c.stream, c.kp, ps,
-                               (const T*)c.pop_in, (T*)c.pop_out, c.aux_f, c.aux_d, c.tgt_in, c.tgt_out, remap(c));
-        else
-            hipLaunchKernelGGL((k_step<L, ST, FAM, false, FM>), grid, dim3(GEN_BLOCK), 0, c.stream, c.kp, ps,
-                               (const T*)c.pop_in, (T*)c.pop_out, c.aux_f, c.aux_d, c.tgt_in, c.tgt_out, remap(c));
-        return hipGetLastError();
-    }
-
-    // Wall layers of a walled domain: the three planes next to each wall.
-    static PlaneSet wall_layers(const KParams& p) { return PlaneSet{0, 3, nm(p) - 3, 3}; }
-    static PlaneSet inner_planes(const KParams& p) { return PlaneSet{3, nm(p) - 6, 0, 0}; }
-
-    static hipError_t aux(const LaunchCtx& c)
-    {
-        if (!c.kp.walls) return aux_planes(c, all(c.kp), false);
-        hipError_t r = aux_planes(c, wall_layers(c.kp), true);
-        if (r == hipSuccess) r = aux_planes(c, inner_planes(c.kp), false);
-        return r;
-    }
-
-    static hipError_t mark(const LaunchCtx& c, hipEvent_t e)
-    {
-        return e ? hipEventRecord(e, c.stream) : hipSuccess;
-    }
-
-    // The dominant launch of a step between the two timing events.
-    template <class F>
-    static hipError_t timed(const LaunchCtx& c, F&& launch)
-    {
-        hipError_t r = mark(c, c.ev_begin);
-        if (r == hipSuccess) r = launch();
-        if (r == hipSuccess) r = mark(c, c.ev_end);
-        return r;
-    }
-
-    static hipError_t step(const LaunchCtx& c)
-    {
-        hipError_t r = aux(c);
-        if (r != hipSuccess) return r;
-        if (!c.kp.walls) return timed(c, [&] { return step_planes(c, all(c.kp), false); });
-        r = step_planes(c, wall_layers(c.kp), true);
-        if (r == hipSuccess) r = timed(c, [&] { return step_planes(c, inner_planes(c.kp), false); });
-        return r;
-    }
-
-    static void dominant(const LaunchCtx& c, char* name, size_t len, long long* cells)
-    {
-        const int n = nm(c.kp);
-        const int planes = c.kp.walls ? n - 6 : n;
-        if (cells) *cells = (long long)planes * c.kp.nlayer;
-        if (!name || !len) return;
-        snprintf(name, len, "k_step<%s,%d,%d,false,%d>", L::D == 3 ? "D3Q39" : "D2Q37", ST, FAM, FM);
-    }
-
-    static hipError_t fields(const LaunchCtx& c, float* rho, float* u, float* th)
-    {
-        if (FAM == FAM_PTENSOR) {
-            hipError_t r = aux(c);
-            if (r != hipSuccess) return r;
-        }
-        if (c.kp.walls)
-            hipLaunchKernelGGL((k_fields<L, ST, FAM, true, FM>), dim3(nblocks_for(c.kp.N)), dim3(GEN_BLOCK), 0,
-                               c.stream, c.kp, (const T*)c.pop_in, c.aux_f, c.aux_d, c.tgt_in, rho, u, th);
-        else
-            hipLaunchKernelGGL((k_fields<L, ST, FAM, false, FM>), dim3(nblocks_for(c.kp.N)), dim3(GEN_BLOCK), 0,
-                               c.stream, c.kp, (const T*)c.pop_in, c.aux_f, c.aux_d, c.tgt_in, rho, u, th);
-        return hipGetLastError();
-    }
-
-    static hipError_t reduce(const LaunchCtx& c, double* out)
-    {
-        if (FAM == FAM_PTENSOR) {
-            hipError_t r = aux(c);
-            if (r != hipSuccess) return r;
-        }
-        const int nb = nblocks_for(c.kp.N);
-        if (nb > c.max_partials) return hipErrorInvalidValue;
-        if (c.kp.walls)
-            hipLaunchKernelGGL((k_reduce<L, ST, FAM, true, FM>), dim3(nb), dim3(GEN_BLOCK), 0, c.stream, c.kp,
-                               (const T*)c.pop_in, c.aux_f, c.aux_d, c.tgt_in, c.partials);
-        else
-            hipLaunchKernelGGL((k_reduce<L, ST, FAM, false, FM>), dim3(nb), dim3(GEN_BLOCK), 0, c.stream, c.kp,
-                               (const T*)c.pop_in, c.aux_f, c.aux_d, c.tgt_in, c.partials);
-        hipError_t r = hipGetLastError();
-        if (r != hipSuccess) return r;
-        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, c.stream, c.partials, nb, out);
-        return hipGetLastError();
-    }
-};
-
-template <class L, int ST, int FM>
-static hipError_t dispatch_family(const LaunchCtx& c, int op, const float* a, const float* b, const float* d,
-                                  float* o1, float* o2, float* o3, double* dout)
-{
-#define HOLB_OPS(FAM)                                                  \
-    switch (op) {                                                      \
-    case 0: return Launch<L, ST, FAM, FM>::init(c, a, b, d);           \
-    case 1: return Launch<L, ST, FAM, FM>::step(c);                    \
-    case 2: return Launch<L, ST, FAM, FM>::aux(c);                     \
-    case 3: return Launch<L, ST, FAM, FM>::fields(c, o1, o2, o3);      \
-    case 4: return Launch<L, ST, FAM, FM>::reduce(c, dout);            \
-    }
-    switch (c.family) {
-    case FAM_LOCAL: HOLB_OPS(FAM_LOCAL) break;
-    case FAM_THERMAL: HOLB_OPS(FAM_THERMAL) break;
-    case FAM_PTENSOR: HOLB_OPS(FAM_PTENSOR) break;
-    }
-#undef HOLB_OPS
-    return hipErrorInvalidValue;
-}
-
-template <class L>
-static hipError_t dispatch_storage(const LaunchCtx& c, int op, const float* a, const float* b, const float* d,
-                                   float* o1, float* o2, float* o3, double* dout)
-{
-    switch (c.storage) {
-    // per-plane frames are FP32 only (validated on the host)
-    case ST_F32:
-        if (c.frames == FM_PLANE) return dispatch_family<L, ST_F32, FM_PLANE>(c, op, a, b, d, o1, o2, o3, dout);
-        return dispatch_family<L, ST_F32, FM_CELL>(c, op, a, b, d, o1, o2, o3, dout);
-    case ST_F16: return dispatch_family<L, ST_F16, FM_CELL>(c, op, a, b, d, o1, o2, o3, dout);
-    case ST_BF16: return dispatch_family<L, ST_BF16, FM_CELL>(c, op, a, b, d, o1, o2, o3, dout);
-    }
-    return hipErrorInvalidValue;
-}
 
 static hipError_t dispatch(const LaunchCtx& c, int op, const float* a = nullptr, const float* b = nullptr,
                            const float* d = nullptr, float* o1 = nullptr, float* o2 = nullptr,
                            float* o3 = nullptr, double* dout = nullptr)
 {
-    if (c.lattice == 0) return dispatch_storage<D2Q37>(c, op, a, b, d, o1, o2, o3, dout);
-    if (c.lattice == 1) return dispatch_storage<D3Q39>(c, op, a, b, d, o1, o2, o3, dout);
+    const bool sixteen = c.storage != ST_F32;
+    if (c.lattice == 0)
+        return sixteen ? dispatch_d2_16(c, op, a, b, d, o1, o2, o3, dout) : dispatch_d2_f32(c, op, a, b, d, o1, o2, o3, dout);
+    if (c.lattice == 1)
+        return sixteen ? dispatch_d3_16(c, op, a, b, d, o1, o2, o3, dout) : dispatch_d3_f32(c, op, a, b, d, o1, o2, o3, dout);
     return hipErrorInvalidValue;
 }
 
@@ -443,35 +35,17 @@ hipError_t launch_reduce(const LaunchCtx& c, double* out_dev)
 }
 int reduce_blocks(const LaunchCtx& c) { return nblocks_for(c.kp.N); }
 
-template <class L, int ST>
-static void dominant_family(const LaunchCtx& c, char* name, size_t len, long long* cells)
-{
-    long long n = 0;
-    switch (c.family) {
-    case FAM_LOCAL: Launch<L, ST, FAM_LOCAL, FM_CELL>::dominant(c, nullptr, 0, &n); break;
-    case FAM_THERMAL: Launch<L, ST, FAM_THERMAL, FM_CELL>::dominant(c, nullptr, 0, &n); break;
-    default: Launch<L, ST, FAM_PTENSOR, FM_CELL>::dominant(c, nullptr, 0, &n); break;
-    }
-    if (cells) *cells = n;
-    // kernel template arguments as a profiler lists them
-    if (name && len)
-        snprintf(name, len, "k_step<%s,%d,%d,false,%d>", L::D == 3 ? "D3Q39" : "D2Q37", ST, c.family, c.frames);
-}
-
-template <class L>
-static void dominant_storage(const LaunchCtx& c, char* name, size_t len, long long* cells)
-{
-    switch (c.storage) {
-    case ST_F32: dominant_family<L, ST_F32>(c, name, len, cells); break;
-    case ST_F16: dominant_family<L, ST_F16>(c, name, len, cells); break;
-    default: dominant_family<L, ST_BF16>(c, name, len, cells); break;
-    }
-}
-
+// The dominant kernel of a step is the collision of the cells away from the
+// wall layers (every cell in a periodic domain).
 void dominant_kernel(const LaunchCtx& c, char* name, size_t len, long long* cells)
 {
-    if (c.lattice == 0) dominant_storage<D2Q37>(c, name, len, cells);
-    else dominant_storage<D3Q39>(c, name, len, cells);
+    const int n = c.lattice == 1 ? c.kp.nz : c.kp.ny;
+    const int planes = c.kp.walls ? n - 6 : n;
+    if (cells) *cells = (long long)planes * c.kp.nlayer;
+    // kernel template arguments as a profiler lists them
+    if (name && len)
+        snprintf(name, len, "k_step<%s,%d,%d,false,%d>", c.lattice == 1 ? "D3Q39" : "D2Q37", c.storage, c.family,
+                 c.frames);
 }
 
 int num_variants(const LaunchCtx&) { return 3; }

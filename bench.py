@@ -132,6 +132,27 @@ def bench_batched(args):
     g1.record(stream)
     torch.cuda.synchronize()
     graph_ms = g0.elapsed_time(g1) / args.steps
+    # the plain alternative: the same runs advanced one at a time, each as its
+    # own simulation (same frames as the batch)
+    sims = []
+    for r in runs:
+        sm = holb.Sim(dict(r["config"], frames=2))
+        sm.init(r["rho"], r["u"], r["theta"])
+        sims.append(sm)
+    for sm in sims:
+        sm.step(1)
+    torch.cuda.synchronize()
+    single_steps = 10
+    s0 = torch.cuda.Event(enable_timing=True)
+    s1 = torch.cuda.Event(enable_timing=True)
+    s0.record(stream)
+    for sm in sims:
+        sm.step(single_steps)
+    s1.record(stream)
+    torch.cuda.synchronize()
+    single_ms = s0.elapsed_time(s1) / single_steps
+    for sm in sims:
+        sm.close()
     bpc = 2 * 37 * 4
     achieved = bpc * kcells / (kern_ms * 1e-3) / 1e9
     line = {
@@ -149,7 +170,9 @@ def bench_batched(args):
         "dtype": "f32",
         "data": "synthetic (seeded fields of the workload recipe)",
         "config": {"workload": "d2q37_batched_512_runs", "runs": len(runs), "cells": cells,
-                   "variant": variant, "graph_replay_ms_per_step": round(graph_ms, 5)},
+                   "variant": variant, "graph_replay_ms_per_step": round(graph_ms, 5),
+                   "one_run_at_a_time_ms_per_step": round(single_ms, 5),
+                   "one_run_at_a_time_mlups": round(cells / (single_ms * 1e-3) / 1e6, 2)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kernel,
                      "kernel_ms": round(kern_ms, 5), "cells_per_launch": kcells, "alg_bytes_per_cell": bpc},

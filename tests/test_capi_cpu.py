@@ -120,6 +120,32 @@ def test_create_is_host_only_and_checks_workspace():
     # Q planes + one frame (2 x binary16) per cell (periodic FP32: per-cell frames)
     assert sb.value == 37 * 1024 * 4 + 1024 * 4
     assert holb.holb_get_state(h, ctypes.c_void_p(fake), sb.value - 4) == holb.ESIZE
+    assert holb.holb_set_state(h, ctypes.c_void_p(fake), sb.value + 4) == holb.ESIZE
+    assert holb.holb_timing_stop(h, None, None, None, None, 0) == holb.OK  # nothing timed: no event touched
+    assert holb.holb_destroy(h) == holb.OK
+
+
+@pytest.mark.parametrize("walls,storage,frames,per_cell", [
+    (1, 0, 0, False), (1, 0, 1, True), (0, 0, 0, True), (0, 0, 2, False), (1, 1, 0, True), (0, 2, 0, True)])
+def test_state_layout_by_frame_mode(walls, storage, frames, per_cell):
+    """The raw state holds the Q planes, then one frame word per cell (per-cell
+    frames) or the per-plane table of 2 + 7 NS floats per plane; AUTO picks
+    per-plane frames for FP32 with walls only."""
+    nx, ny, nz = 24, 20, 16
+    cfg = holb.make_config(dict(lattice=1, nx=nx, ny=ny, nz=nz, tau_hat=0.8, sources=3, prandtl=0.7,
+                                g=(0, 0, -1e-5), walls=walls, storage=storage, frames=frames, rho0=1.0,
+                                theta0=1.0))
+    need = ctypes.c_size_t()
+    assert holb.holb_workspace_size(ctypes.byref(cfg), ctypes.byref(need)) == holb.OK
+    h = ctypes.c_void_p()
+    assert holb.holb_create(ctypes.byref(cfg), ctypes.c_void_p(1 << 40), need.value, None, ctypes.byref(h)) == holb.OK
+    sb = ctypes.c_size_t()
+    assert holb.holb_state_bytes(h, ctypes.byref(sb)) == holb.OK
+    N = nx * ny * nz
+    elem = 4 if storage == 0 else 2
+    pitch = -(-N // (256 // elem)) * (256 // elem)
+    extra = -(-N * 4 // 256) * 256 if per_cell else (2 + 7 * 6) * nz * 4
+    assert sb.value == 39 * pitch * elem + extra
     assert holb.holb_destroy(h) == holb.OK
 
 

@@ -518,11 +518,16 @@ int orc_init(orc_sim *s, const double *rho, const double *u, const double *theta
 }
 
 /* Section 4.3, Eqs. (4.7)-(4.8): the populations streamed in from outside the
- * domain (unknown set U) are rebuilt as f_i = f_ibar + f^eq_i(tgt) - f^eq_i(loc);
- * the local state fills U with the target equilibrium.  Targets: wall nodes
- * (first and last layer along the wall-normal axis) take the previous-step
- * density with the wall velocity and temperature; fluid nodes take their own
- * previous-step fields. */
+ * domain (unknown set U) are rebuilt as f_i = f_ibar + f^eq_i(tgt) - f^eq_ibar(loc),
+ * i.e. the target equilibrium plus the non-equilibrium part of the opposite
+ * population; the local state fills U with the target equilibrium.  The
+ * opposite index on the local equilibrium is the reading under which a node
+ * already at the target state is left unchanged and a moving wall imposes its
+ * velocity (the Couette validation of Section 5.1); with the index i on both
+ * equilibria the unknowns reduce to plain bounce-back at that state.  Targets:
+ * wall nodes (first and last layer along the wall-normal axis) take the
+ * previous-step density with the wall velocity and temperature; fluid nodes
+ * take their own previous-step fields. */
 static void tms_fill(orc_sim *s)
 {
     if (!s->cfg.walls) return;
@@ -571,7 +576,7 @@ static void tms_fill(orc_sim *s)
         double tl = s->cfg.isothermal ? 1.0 : (el - rl * dot3(ul, ul) + dot3(ul, Fl)) / (rl * s->D * L->c0sq);
         orc_feq(s->cfg.lattice, rl, ul, tl, fel);
         for (int i = 0; i < L->Q; ++i)
-            if (unknown[i]) s->f[i * N + cell] = s->f[L->opp[i] * N + cell] + fet[i] - fel[i];
+            if (unknown[i]) s->f[i * N + cell] = s->f[L->opp[i] * N + cell] + fet[i] - fel[L->opp[i]];
     }
 }
 

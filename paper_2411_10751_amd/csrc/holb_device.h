@@ -292,8 +292,11 @@ __device__ __forceinline__ void macro_from_moments(const KParams& p, const Frame
 }
 
 // Section 4.3, Eqs. (4.7)-(4.8): rebuild the populations that streamed in
-// from outside the walls, f_i = f_ibar + f^eq_i(tgt) - f^eq_i(loc), where the
-// local state fills the unknown set with the target equilibrium.  unk has bit
+// from outside the walls, f_i = f_ibar + f^eq_i(tgt) - f^eq_ibar(loc), where the
+// local state fills the unknown set with the target equilibrium.  The local
+// equilibrium is taken at the opposite index (non-equilibrium bounce-back):
+// a node at the target state then stays there, and a moving wall imposes its
+// velocity.  unk has bit
 // i set for unknown direction i; tgt holds the previous-step (rho, u[D],
 // theta) of this node; wall = 0/1 for a wall node (first/last layer), -1 for
 // a fluid node, whose target is its own previous-step state.
@@ -331,7 +334,7 @@ __device__ __forceinline__ void tms_fill(const KParams& p, const Frame& fr, floa
     for (int i = 0; i < L::Q; ++i) {
         if ((unk >> i) & 1ull) {
             const double et = (double)rt * (1.0 + feq_t<L, double>(i, ut, tbt));
-            const double el = (double)loc.rho * (1.0 + feq_t<L, double>(i, loc.u, loc.thb));
+            const double el = (double)loc.rho * (1.0 + feq_t<L, double>(LL::opp(i), loc.u, loc.thb));
             h[i] = h[LL::opp(i)] + (float)(et - el);
         }
     }

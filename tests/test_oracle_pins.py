@@ -473,6 +473,88 @@ def test_thermal_wave_prandtl(pr):
     assert abs(kappa / (L.c0sq * 0.3 / pr) - 1) < 0.005
 
 
+# ---------------------------------------------------------------- walls
+
+
+@pytest.mark.parametrize("lattice,isothermal", [(orc.D2Q37, 1), (orc.D2Q37, 0), (orc.D3Q39, 1),
+                                                (orc.D3Q39, 0)])
+def test_tms_wall_state_is_fixed_point(lattice, isothermal):
+    """Section 4.3: with both walls at one state (tangential velocity, wall
+    temperature) and the fluid at rest in that state, the closure of Eq. (4.7)
+    reconstructs the unknown populations as the target equilibrium and the
+    uniform state persists to rounding.  A wrong index on either equilibrium
+    (plain bounce-back of the wall velocity) or a target that ignores the wall
+    velocity moves it by O(u_wall)."""
+    L = orc.Lattice(lattice)
+    shape = (10, 3) if L.D == 2 else (10, 3, 3)
+    uw = (0.05, 0.0, 0.0) if L.D == 2 else (0.04, -0.03, 0.0)
+    tw = 1.0 if isothermal else 0.9
+    s = orc.Sim(lattice, *shape[::-1], tau_hat=0.7, isothermal=isothermal, walls=1,
+                theta_wall=(tw, tw), u_wall=(uw, uw))
+    u = np.zeros((L.D,) + shape)
+    for a in range(L.D):
+        u[a] = uw[a]
+    s.init(np.ones(shape), u, np.full(shape, tw))
+    s.step(40)
+    # the stored state is post-streaming: slots streamed in from outside the
+    # walls are empty (NaN) until the closure of the next step fills them
+    f = s.get_state().reshape(L.Q, -1)
+    known = np.isfinite(f)
+    # per wall, layer k (k = 0, 1, 2 from the wall) misses the c_n > k populations
+    n_unknown = sum(np.count_nonzero(np.abs(L.c[:, L.D - 1]) > k) for k in range(3))
+    assert (~known).sum() == n_unknown * int(np.prod(shape[1:]))
+    fe = np.broadcast_to(orc.feq(lattice, 1.0, np.array(uw[:L.D]), tw)[:, None], f.shape)
+    assert np.abs(f[known] - fe[known]).max() < 1e-13
+    r, u1, th = s.fields()
+    assert np.abs(r - 1).max() < 1e-13 and np.abs(th - tw).max() < 1e-13
+    for a in range(L.D):
+        assert np.abs(u1[a] - uw[a]).max() < 1e-13
+
+
+def _channel(kind, ny=30, nu=0.1, u0=0.0185, steps=30000):
+    """Steady isothermal channel flow between TMS walls (D2Q37, one column,
+    walls normal to y): Couette with the top wall at u0, or Poiseuille driven
+    by a body force of Eq. (3.3) sized for a centre-line speed u0."""
+    L = orc.Lattice(orc.D2Q37)
+    tau = 0.5 + nu / L.c0sq
+    H = ny - 1
+    g = 8 * u0 * nu / H ** 2 if kind == "poiseuille" else 0.0
+    s = orc.Sim(orc.D2Q37, 1, ny, tau_hat=tau, sources=orc.SRC_BODY if g else 0, isothermal=1,
+                g=(g, 0, 0), walls=1, u_wall=((0, 0, 0), (u0 if kind == "couette" else 0.0, 0, 0)))
+    s.init(np.ones((ny, 1)), np.zeros((2, ny, 1)), np.ones((ny, 1)))
+    s.step(steps)
+    r, u, _ = s.fields()
+    return u[0, :, 0], u[1, :, 0], g, nu
+
+
+def test_tms_couette_profile():
+    """Section 5.1, Eq. (5.1) (isothermal limit): between a fixed and a moving
+    TMS wall the steady profile is linear; the wall nodes carry the wall
+    velocities and the effective walls lie within a quarter node of them."""
+    u0 = 0.0185
+    ux, uy, _, _ = _channel("couette", u0=u0)
+    y = np.arange(ux.size)
+    b, a = np.polyfit(y, ux, 1)
+    assert np.abs(ux - (a + b * y)).max() < 2e-3 * u0
+    assert abs(ux[0]) < 0.01 * u0 and abs(ux[-1] - u0) < 0.01 * u0
+    assert abs(-a / b) < 0.25 and abs((u0 - a) / b - (ux.size - 1)) < 0.25
+    assert np.abs(uy).max() < 1e-9
+
+
+def test_tms_poiseuille_profile():
+    """Body-force-driven channel between TMS walls: the steady profile is the
+    parabola with curvature -g/nu (nu = c0^2 (tau_hat - 1/2)), symmetric about
+    the centre line, vanishing within a quarter node of the wall nodes."""
+    ux, uy, g, nu = _channel("poiseuille")
+    y = np.arange(ux.size)
+    c = np.polyfit(y, ux, 2)
+    assert abs(2 * c[0] / (-g / nu) - 1) < 0.005
+    assert np.abs(ux - ux[::-1]).max() < 1e-12
+    z = np.sort(np.roots(c).real)
+    assert abs(z[0]) < 0.25 and abs(z[1] - (ux.size - 1)) < 0.25
+    assert np.abs(uy).max() < 1e-12
+
+
 @pytest.mark.slow
 def test_laplace_law_static_droplet():
     """Static droplet (Section 5.4, Eq. 5.11 profile): the pressure jump

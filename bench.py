@@ -51,17 +51,17 @@ def cpu_baseline(name, storage):
     from oracle import orc
     from paper_2411_10751_amd import inputs
     if name == "rb3d":
-        w = inputs.rayleigh_benard_3d(n=64, steps=20)
-        sample = "D3Q39 Rayleigh-Benard 64^3 with walls, body+thermal, 20 steps"
+        w = inputs.rayleigh_benard_3d(n=64, steps=300)
+        sample = "D3Q39 Rayleigh-Benard 64^3 with walls, body+thermal, 300 steps"
     elif name == "thermal2d":
-        w = inputs.thermal_2d(n=256, steps=40)
-        sample = "D2Q37 thermal 256^2, 40 steps"
+        w = inputs.thermal_2d(n=256, steps=1500)
+        sample = "D2Q37 thermal 256^2, 1500 steps"
     elif name == "ptensor2d":
-        w = inputs.ptensor_2d(n=256, steps=40, ndrops=6, rmin=10, rmax=20, gap=8)
-        sample = "D2Q37 pressure tensor 256^2 droplets, 40 steps"
+        w = inputs.ptensor_2d(n=256, steps=1000, ndrops=6, rmin=10, rmax=20, gap=8)
+        sample = "D2Q37 pressure tensor 256^2 droplets, 1000 steps"
     else:
-        w = inputs.body_force_2d(n=256, steps=40)
-        sample = "D2Q37 body force 256^2, 40 steps"
+        w = inputs.body_force_2d(n=256, steps=1500)
+        sample = "D2Q37 body force 256^2, 1500 steps"
     c = w["config"]
     s = orc.Sim(c["lattice"], c["nx"], c["ny"], c.get("nz", 1), tau_hat=c["tau_hat"], sources=c["sources"],
                 isothermal=c.get("isothermal", 0), g=c["g"], prandtl=c["prandtl"], eos_a=c["eos_a"],
@@ -188,11 +188,11 @@ def bench_batched(args):
             sim = orc.Sim(c["lattice"], c["nx"], c["ny"], 1, tau_hat=c["tau_hat"], sources=c["sources"],
                           g=c["g"], prandtl=c["prandtl"])
             sim.init(r["rho"].astype(np.float64), r["u"].astype(np.float64), r["theta"].astype(np.float64))
-            sim.step(20)
-            ncell += c["nx"] * c["ny"] * 20
+            sim.step(250)
+            ncell += c["nx"] * c["ny"] * 250
         dt = time.perf_counter() - t0
         line["cpu_baseline"] = {"value": round(ncell / dt / 1e6, 4), "unit": "MLUPS", "cores": orc.num_threads(),
-                                "kind": "oracle", "sample": "first 16 runs of the batch, 20 steps each (FP64, %.1f s)"
+                                "kind": "oracle", "sample": "first 16 runs of the batch, 250 steps each (FP64, %.1f s)"
                                 % dt}
     print(json.dumps(line), flush=True)
 

@@ -66,7 +66,7 @@ def cpu_baseline(name, storage):
     s = orc.Sim(c["lattice"], c["nx"], c["ny"], c.get("nz", 1), tau_hat=c["tau_hat"], sources=c["sources"],
                 isothermal=c.get("isothermal", 0), g=c["g"], prandtl=c["prandtl"], eos_a=c["eos_a"],
                 eos_b=c["eos_b"], eos_T=c["eos_T"], sc_G=c["sc_G"], ptensor_k=c["ptensor_k"],
-                walls=c["walls"], theta_wall=c["theta_wall"], u_wall=c["u_wall"])
+                walls=c["walls"], theta_wall=c["theta_wall"], u_wall=c["u_wall"], eos=c.get("eos", 0))
     s.init(w["rho"].astype(np.float64), w["u"].astype(np.float64), w["theta"].astype(np.float64))
     s.step(1)
     t0 = time.perf_counter()

@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define HOLB_ABI_VERSION 2
+#define HOLB_ABI_VERSION 3
 
 typedef int32_t holb_status;
 #define HOLB_OK 0
@@ -81,6 +81,13 @@ typedef int32_t holb_status;
 #define HOLB_FRAMES_CELL 1
 #define HOLB_FRAMES_PLANE 2
 
+/* Equation of state of the pseudopotential (HOLB_SRC_PTENSOR), parameters
+ * eos_a, eos_b, eos_T: van der Waals p = rho T / (1 - b rho) - a rho^2, or
+ * Carnahan-Starling (Section 5.4, Eq. 5.9, R_g = 1)
+ * p = rho T (1 + e + e^2 - e^3) / (1 - e)^3 - a rho^2 with e = b rho / 4. */
+#define HOLB_EOS_VDW 0
+#define HOLB_EOS_CS 1
+
 #define HOLB_STORE_F32 0
 #define HOLB_STORE_F16DEV 1
 #define HOLB_STORE_BF16DEV 2
@@ -99,9 +106,10 @@ typedef struct {
     int32_t isothermal;   /* 1: theta held at 1 (multiphase mode of Section 5.4) */
     double g[3];          /* body-force acceleration, F = rho g (HOLB_SRC_BODY) */
     double prandtl;       /* Prandtl number of H_i (HOLB_SRC_THERMAL), > 0 */
-    double eos_a, eos_b, eos_T; /* van der Waals p = rho T / (1 - b rho) - a rho^2 */
+    double eos_a, eos_b, eos_T; /* parameters a, b, T of the equation of state (eos) */
     double sc_G;          /* pseudopotential coupling G (the paper uses -1) */
-    double ptensor_k;     /* free parameter k of P_i, Eq. (3.12) */
+    double ptensor_k;     /* free parameter k of P_i, Eq. (3.12), evaluated in Hermite units: the
+                           * paper's Carnahan-Starling optimum 3.02 is 3.02 c0^4 here */
     int32_t storage;      /* HOLB_STORE_* */
     double rho0, theta0, u0[3]; /* background state: u0 (with rho0, theta0) centres the 16-bit
                                  * storage; theta0 is the offset of the temperature field of
@@ -110,6 +118,7 @@ typedef struct {
     double theta_wall[2]; /* wall temperatures: [0] at index 0, [1] at index n-1 */
     double u_wall[2][3];  /* wall velocities, same order */
     int32_t frames;       /* HOLB_FRAMES_*: reference of the stored populations */
+    int32_t eos;          /* HOLB_EOS_*: equation of state of the pseudopotential */
 } holb_config;
 
 typedef struct holb_sim holb_sim;

@@ -348,20 +348,40 @@ int orc_vdw_pressure(double a, double b, double T, double rho, double *p)
     return ORC_OK;
 }
 
+/* Carnahan-Starling equation of state, Eq. (5.9) with R_g = 1:
+ * p = rho T (1 + e + e^2 - e^3) / (1 - e)^3 - a rho^2, e = b rho / 4. */
+int orc_cs_pressure(double a, double b, double T, double rho, double *p)
+{
+    double e = 0.25 * b * rho;
+    if (!(rho > 0) || !(e < 1.0)) return ORC_ENUMERIC;
+    double d = 1.0 - e;
+    *p = rho * T * (1.0 + e + e * e - e * e * e) / (d * d * d) - a * rho * rho;
+    return ORC_OK;
+}
+
 /* Pseudopotential of Eq. (3.8), psi = sqrt(2 (p_EOS - rho theta) / G) in
- * Hermite units; in lattice units rho theta -> rho c0^2 and the argument is
- * divided by c0^2, so that F^SC ~ -grad(p_EOS - rho c0^2). */
-int orc_psi(int lattice, double a, double b, double T, double G, double rho, double *psi)
+ * Hermite units with theta = 1 (the multiphase runs hold theta at 1, Section
+ * 5.4); in lattice units rho theta -> rho c0^2 and the argument is divided by
+ * c0^2, so that F^SC ~ -grad(p_EOS - rho c0^2). */
+int orc_psi_eos(int lattice, int eos, double a, double b, double T, double G, double rho, double *psi)
 {
     const orc_lattice *L = lattice_cached(lattice);
     if (!L) return ORC_EINVAL;
     double p;
-    int rc = orc_vdw_pressure(a, b, T, rho, &p);
+    int rc;
+    if (eos == ORC_EOS_VDW) rc = orc_vdw_pressure(a, b, T, rho, &p);
+    else if (eos == ORC_EOS_CS) rc = orc_cs_pressure(a, b, T, rho, &p);
+    else return ORC_EINVAL;
     if (rc) return rc;
     double arg = 2.0 * (p - rho * L->c0sq) / (G * L->c0sq);
     if (!(arg >= 0.0)) return ORC_ENUMERIC;
     *psi = sqrt(arg);
     return ORC_OK;
+}
+
+int orc_psi(int lattice, double a, double b, double T, double G, double rho, double *psi)
+{
+    return orc_psi_eos(lattice, ORC_EOS_VDW, a, b, T, G, rho, psi);
 }
 
 static long wrap(long x, long n)
@@ -448,6 +468,7 @@ int orc_create(const orc_config *cfg, orc_sim **out)
     if (src & ~(ORC_SRC_BODY | ORC_SRC_THERMAL | ORC_SRC_PTENSOR)) return ORC_EINVAL;
     if ((src & ORC_SRC_THERMAL) && (cfg->isothermal || !(cfg->prandtl > 0))) return ORC_EUNSUPPORTED;
     if ((src & ORC_SRC_PTENSOR) && (!cfg->isothermal || cfg->walls)) return ORC_EUNSUPPORTED;
+    if (cfg->eos != ORC_EOS_VDW && cfg->eos != ORC_EOS_CS) return ORC_EINVAL;
     orc_sim *s = calloc(1, sizeof *s);
     if (!s) return ORC_EINVAL;
     s->cfg = *cfg;
@@ -610,7 +631,7 @@ static int macroscopic(orc_sim *s)
 #pragma omp parallel for schedule(static) reduction(| : bad)
 #endif
         for (long cell = 0; cell < N; ++cell)
-            if (orc_psi(cf->lattice, cf->eos_a, cf->eos_b, cf->eos_T, cf->sc_G, s->rho[cell], &s->psi[cell]))
+            if (orc_psi_eos(cf->lattice, cf->eos, cf->eos_a, cf->eos_b, cf->eos_T, cf->sc_G, s->rho[cell], &s->psi[cell]))
                 bad = 1;
         if (bad) return ORC_ENUMERIC;
         orc_sc_force_field(cf->lattice, s->dims[0], s->dims[1], s->dims[2], s->psi, cf->sc_G, s->Fsc);

@@ -32,6 +32,9 @@ extern "C" {
 #define ORC_SRC_THERMAL 2u
 #define ORC_SRC_PTENSOR 4u
 
+#define ORC_EOS_VDW 0        /* p = rho*T/(1-b*rho) - a*rho^2 */
+#define ORC_EOS_CS 1         /* Carnahan-Starling, Eq. (5.9), R_g = 1 */
+
 #define ORC_QMAX 39
 
 typedef struct {
@@ -42,12 +45,13 @@ typedef struct {
     int isothermal;        /* 1: theta held at 1 (Section 5.4) */
     double g[3];           /* body-force acceleration, F = rho*g */
     double prandtl;        /* Pr of the thermal-dissipation source */
-    double eos_a, eos_b, eos_T; /* van der Waals p = rho*T/(1-b*rho) - a*rho^2 */
+    double eos_a, eos_b, eos_T; /* parameters a, b, T of the equation of state (field eos) */
     double sc_G;           /* pseudopotential coupling G (paper: -1) */
     double ptensor_k;      /* free parameter k of Eq. (3.12) */
     int walls;             /* 0: periodic; 1: TMS walls normal to last axis */
     double theta_wall[2];  /* [0] low wall (index 0), [1] high wall */
     double u_wall[2][3];   /* wall velocities, same order */
+    int eos;               /* ORC_EOS_VDW or ORC_EOS_CS */
 } orc_config;
 
 typedef struct {
@@ -71,7 +75,10 @@ int orc_src_thermal(int lattice, double rho, double theta, double prandtl,
 int orc_src_ptensor(int lattice, double tau_hat, double k, double G,
                     const double *Fsc, double psi, double *out);
 int orc_vdw_pressure(double a, double b, double T, double rho, double *p);
+int orc_cs_pressure(double a, double b, double T, double rho, double *p);
 int orc_psi(int lattice, double a, double b, double T, double G, double rho, double *psi);
+/* psi of Eq. (3.8) for either equation of state (orc_psi is the van der Waals case). */
+int orc_psi_eos(int lattice, int eos, double a, double b, double T, double G, double rho, double *psi);
 /* F^SC of Eq. (3.8) for a periodic psi field (nz == 1 for 2D). */
 int orc_sc_force_field(int lattice, int nx, int ny, int nz, const double *psi, double G,
                        double *Fsc);

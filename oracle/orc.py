@@ -17,6 +17,8 @@ _SRC = os.path.join(_HERE, "holb_oracle.c")
 
 D2Q37 = 0
 D3Q39 = 1
+EOS_VDW = 0
+EOS_CS = 1
 SRC_BODY = 1
 SRC_THERMAL = 2
 SRC_PTENSOR = 4
@@ -52,6 +54,7 @@ class _Config(ctypes.Structure):
         ("walls", ctypes.c_int),
         ("theta_wall", ctypes.c_double * 2),
         ("u_wall", (ctypes.c_double * 3) * 2),
+        ("eos", ctypes.c_int),
     ]
 
 
@@ -82,6 +85,8 @@ def lib():
         _lib.orc_src_ptensor.argtypes = [ctypes.c_int, d, d, d, dp, d, dp]
         _lib.orc_vdw_pressure.argtypes = [d, d, d, d, dp]
         _lib.orc_psi.argtypes = [ctypes.c_int, d, d, d, d, d, dp]
+        _lib.orc_cs_pressure.argtypes = [d, d, d, d, dp]
+        _lib.orc_psi_eos.argtypes = [ctypes.c_int, ctypes.c_int, d, d, d, d, d, dp]
         _lib.orc_sc_force_field.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                             dp, d, dp]
         _lib.orc_create.argtypes = [P(_Config), P(ctypes.c_void_p)]
@@ -178,9 +183,15 @@ def vdw_pressure(a, b, T, rho):
     return p.value
 
 
-def psi(lattice, a, b, T, G, rho):
+def cs_pressure(a, b, T, rho):
     p = ctypes.c_double()
-    _check(lib().orc_psi(lattice, a, b, T, G, float(rho), ctypes.byref(p)), "psi")
+    _check(lib().orc_cs_pressure(a, b, T, float(rho), ctypes.byref(p)), "cs_pressure")
+    return p.value
+
+
+def psi(lattice, a, b, T, G, rho, eos=EOS_VDW):
+    p = ctypes.c_double()
+    _check(lib().orc_psi_eos(lattice, eos, a, b, T, G, float(rho), ctypes.byref(p)), "psi")
     return p.value
 
 
@@ -199,12 +210,12 @@ class Sim:
 
     Keyword arguments mirror the GPU configuration: lattice, nx, ny, nz,
     tau_hat, sources, isothermal, g, prandtl, eos_a, eos_b, eos_T, sc_G,
-    ptensor_k, walls, theta_wall (low, high), u_wall (low, high).
+    ptensor_k, walls, theta_wall (low, high), u_wall (low, high), eos.
     """
 
     def __init__(self, lattice, nx, ny, nz=1, tau_hat=0.8, sources=0, isothermal=0, g=(0, 0, 0),
                  prandtl=1.0, eos_a=0.0, eos_b=0.0, eos_T=0.0, sc_G=-1.0, ptensor_k=0.0, walls=0,
-                 theta_wall=(1.0, 1.0), u_wall=((0, 0, 0), (0, 0, 0))):
+                 theta_wall=(1.0, 1.0), u_wall=((0, 0, 0), (0, 0, 0)), eos=EOS_VDW):
         c = _Config()
         c.lattice, c.nx, c.ny, c.nz = lattice, nx, ny, nz
         c.tau_hat, c.sources, c.isothermal = tau_hat, sources, int(isothermal)
@@ -213,6 +224,7 @@ class Sim:
         c.prandtl = prandtl
         c.eos_a, c.eos_b, c.eos_T, c.sc_G, c.ptensor_k = eos_a, eos_b, eos_T, sc_G, ptensor_k
         c.walls = int(walls)
+        c.eos = int(eos)
         c.theta_wall[0], c.theta_wall[1] = theta_wall
         for w in range(2):
             for a in range(3):

@@ -345,7 +345,7 @@ __device__ __forceinline__ void aux_cell(const KParams& p, const typename Codec<
     load_state<L, ST, WALLS, FM>(p, fin, tgt_in, x, y, z, f, fo, dr, j, ed);
     if (FAM == FAM_PTENSOR) {
         bool bad = false;
-        aux_d[cell] = psi_vdw(p, (double)fo.rho + (double)dr, L::c0sq, bad);
+        aux_d[cell] = psi_eos(p, (double)fo.rho + (double)dr, L::c0sq, bad);
         if (bad) raise_err(p, HOLB_ERR_EOS_BIT);
     } else {
         const float z3[3] = {0.f, 0.f, 0.f};

@@ -441,13 +441,21 @@ __device__ __forceinline__ void collide(const KParams& p, const Frame& fr, float
     if (CONSERVE) conserve<L>(p, h, m);
 }
 
-// van der Waals pseudopotential of Eq. (3.8) in FP64:
-// psi = sqrt(2 (p_EOS - rho c0^2) / (G c0^2)).
-__device__ __forceinline__ double psi_vdw(const KParams& p, double rho, double c0sq, bool& bad)
+// Pseudopotential of Eq. (3.8) in FP64: psi = sqrt(2 (p_EOS - rho c0^2) / (G c0^2)),
+// with the van der Waals or the Carnahan-Starling (Eq. 5.9) pressure.
+__device__ __forceinline__ double psi_eos(const KParams& p, double rho, double c0sq, bool& bad)
 {
-    const double br = p.eos_b * rho;
-    if (!(rho > 0.0) || !(br < 1.0)) { bad = true; return 0.0; }
-    const double pe = rho * p.eos_T / (1.0 - br) - p.eos_a * rho * rho;
+    double pe;
+    if (p.eos == EOS_CS) {
+        const double e = 0.25 * p.eos_b * rho;
+        if (!(rho > 0.0) || !(e < 1.0)) { bad = true; return 0.0; }
+        const double d = 1.0 - e;
+        pe = rho * p.eos_T * (1.0 + e * (1.0 + e * (1.0 - e))) / (d * d * d) - p.eos_a * rho * rho;
+    } else {
+        const double br = p.eos_b * rho;
+        if (!(rho > 0.0) || !(br < 1.0)) { bad = true; return 0.0; }
+        pe = rho * p.eos_T / (1.0 - br) - p.eos_a * rho * rho;
+    }
     const double arg = 2.0 * (pe - rho * c0sq) / (p.G * c0sq);
     if (!(arg >= 0.0)) { bad = true; return 0.0; }
     return sqrt(arg);

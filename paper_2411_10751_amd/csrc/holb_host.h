@@ -15,6 +15,8 @@
 
 namespace holb {
 
+static_assert(EOS_VDW == HOLB_EOS_VDW && EOS_CS == HOLB_EOS_CS, "equation-of-state codes");
+
 extern thread_local std::string g_last_error;
 
 inline holb_status fail(holb_status code, const char* fmt, ...)
@@ -74,8 +76,10 @@ inline holb_status validate(const holb_config* c)
     if (c->sources & HOLB_SRC_PTENSOR) {
         if (!c->isothermal) return fail(HOLB_EUNSUPPORTED, "pressure-tensor source runs in the isothermal mode");
         if (c->walls) return fail(HOLB_EUNSUPPORTED, "pressure-tensor source with walls is not supported");
-        if (!(c->eos_b > 0) || !(c->eos_T > 0) || !(c->eos_a >= 0) || !std::isfinite(c->eos_a))
-            return fail(HOLB_EINVAL, "van der Waals parameters need a >= 0, b > 0, T > 0");
+        if (c->eos != HOLB_EOS_VDW && c->eos != HOLB_EOS_CS) return fail(HOLB_EINVAL, "eos must be one of HOLB_EOS_*");
+        if (!(c->eos_b > 0) || !(c->eos_T > 0) || !(c->eos_a >= 0) || !std::isfinite(c->eos_a) ||
+            !std::isfinite(c->eos_b) || !std::isfinite(c->eos_T))
+            return fail(HOLB_EINVAL, "equation-of-state parameters need a >= 0, b > 0, T > 0");
         if (!(c->sc_G != 0) || !std::isfinite(c->sc_G)) return fail(HOLB_EINVAL, "sc_G must be non-zero");
         if (!std::isfinite(c->ptensor_k)) return fail(HOLB_EINVAL, "ptensor_k must be finite");
     }
@@ -138,6 +142,7 @@ inline KParams params_of(const holb_config* c)
         const double tau = c->tau_hat - 0.5;
         p.pfac = -(c->ptensor_k / (2.0 * D * tau)) / (c0sq * c->sc_G);
         p.eos_a = c->eos_a; p.eos_b = c->eos_b; p.eos_T = c->eos_T; p.G = c->sc_G;
+        p.eos = c->eos;
     }
     p.rho_ref = (float)c->rho0;
     // the reference temperature only where theta evolves

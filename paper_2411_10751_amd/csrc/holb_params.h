@@ -19,6 +19,8 @@ enum : unsigned { KF_BODY = 1u, KF_ISO = 2u };
 enum FrameMode { FM_CELL = 0, FM_PLANE = 1 };
 
 enum : unsigned { HOLB_ERR_DENSITY_BIT = 1u, HOLB_ERR_THETA_BIT = 2u, HOLB_ERR_EOS_BIT = 4u };
+// equation of state of the pseudopotential (values of HOLB_EOS_*)
+enum : int { EOS_VDW = 0, EOS_CS = 1 };
 
 constexpr int QMAX = 39;
 
@@ -61,6 +63,7 @@ struct KParams {
     float uwall[2][3];
     double pfac;         // -(k / (2 D tau)) / (c0^2 G), tau = tau_hat - 1/2
     double eos_a, eos_b, eos_T, G;
+    int eos;             // EOS_VDW or EOS_CS
     float rho_ref;       // rho0 and theta0 - 1 of the reference state: populations
     float thb_ref;       //   are handled as h_i = f_i / w_i - f^eq_i(rho0, 0, theta0) / w_i
     float dref[QMAX];    // d_i = (f^eq_i(rho0, u0, theta0) - f^eq_i(rho0, 0, theta0)) / w_i (16-bit offset)

@@ -17,8 +17,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libholb.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 FRAMES_AUTO, FRAMES_CELL, FRAMES_PLANE = 0, 1, 2
+EOS_VDW, EOS_CS = 0, 1
 OK, EINVAL, ESIZE, EHIP, ENUMERIC, EUNSUPPORTED, ESTATE = 0, -1, -2, -3, -4, -5, -6
 D2Q37, D3Q39 = 0, 1
 SRC_BODY, SRC_THERMAL, SRC_PTENSOR = 1, 2, 4
@@ -45,6 +46,7 @@ class holb_config(ctypes.Structure):
         ("theta_wall", ctypes.c_double * 2),
         ("u_wall", (ctypes.c_double * 3) * 2),
         ("frames", ctypes.c_int32),
+        ("eos", ctypes.c_int32),
     ]
 
 
@@ -153,6 +155,7 @@ def make_config(cfg):
         for a in range(3):
             c.u_wall[w][a] = float(uu[a])
     c.frames = int(cfg.get("frames", 0))
+    c.eos = int(cfg.get("eos", 0))
     return c
 
 

@@ -65,6 +65,7 @@ def _cfg(**kw):
     (dict(sources=4, isothermal=0, eos_a=0.1, eos_b=0.1, eos_T=0.5), holb.EUNSUPPORTED),
     (dict(sources=4, isothermal=1, eos_a=0.1, eos_b=0.0, eos_T=0.5), holb.EINVAL),
     (dict(sources=4, isothermal=1, eos_a=0.1, eos_b=0.1, eos_T=0.5, walls=1), holb.EUNSUPPORTED),
+    (dict(sources=4, isothermal=1, eos_a=0.1, eos_b=0.1, eos_T=0.5, eos=2), holb.EINVAL),
     (dict(storage=5), holb.EINVAL),
     (dict(storage=1, rho0=0.0), holb.EINVAL),
     (dict(walls=1, ny=6), holb.EINVAL),

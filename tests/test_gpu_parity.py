@@ -113,6 +113,15 @@ def test_ptensor_small_16bit(storage=1):
     assert_parity(g, o, 0, TOL[storage], w["name"] + " st%d" % storage)
 
 
+@pytest.mark.parametrize("storage", [0, 1])
+def test_ptensor_cs_small(storage):
+    """Carnahan-Starling droplets (Section 5.4, Eq. 5.9) at T = 0.8 Tc, density
+    ratio 14, with the paper's optimum k, in FP32 and FP16 storage."""
+    w = inputs.ptensor_cs_2d(n=128, steps=200, ndrops=4, rmin=10.0, rmax=20.0, gap=8.0)
+    g, o = _both(w, storage=storage)
+    assert_parity(g, o, 0, TOL[storage], w["name"] + " st%d" % storage)
+
+
 def _rb(n, nz, steps, **kw):
     """The Rayleigh-Benard recipe on a smaller box with the gravity of the
     256^3 workload (Ra scaled with H^3), so that the small case is as gentle

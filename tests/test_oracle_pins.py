@@ -292,6 +292,78 @@ def test_vdw_maxwell_densities():
     assert abs(orc.vdw_pressure(a, b, T, 2.0) - (2.0 * T / (1 - 2 * b) - 4 * a)) < 1e-15
 
 
+def test_cs_maxwell_densities():
+    """Carnahan-Starling gas of Section 5.4 (Eq. 5.9): the critical point is
+    where dp/drho and d2p/drho2 vanish together (T_c b / a = 0.3773, T_c ~ 0.023
+    as the paper states); Maxwell densities have equal pressure and equal area
+    in specific volume; the input generator carries these values; and the
+    oracle's C equation of state and pseudopotential agree with them."""
+    from scipy.integrate import quad
+    a, b = inputs.CS_A, inputs.CS_B
+    rc, Tc = thermo.cs_critical(a, b)
+    assert abs(Tc * b / a - 0.3773) < 1e-4 and abs(round(Tc, 3) - 0.024) < 1e-12
+    h = 1e-4 * rc
+    d1 = thermo.cs_dpdrho(rc, a, b, Tc)
+    d2 = (thermo.cs_dpdrho(rc + h, a, b, Tc) - thermo.cs_dpdrho(rc - h, a, b, Tc)) / (2 * h)
+    assert abs(d1) < 1e-12 and abs(d2) < 1e-6
+    assert abs(Tc - inputs.CS_TC) < 1e-15
+    for tr in (0.7, 0.8, 0.9):
+        T = tr * Tc
+        rg, rl = thermo.cs_maxwell(a, b, T)
+        pg, pl = thermo.cs_pressure(rg, a, b, T), thermo.cs_pressure(rl, a, b, T)
+        assert abs(pg - pl) < 1e-15
+        area = quad(lambda v: thermo.cs_pressure(1 / v, a, b, T) - pg, 1 / rl, 1 / rg,
+                    epsabs=1e-15, epsrel=1e-13, limit=200)[0]
+        assert abs(area) < 1e-12 * (1 / rg)
+        if tr == 0.8:
+            assert abs(rg - inputs.CS_RHO_G_08) < 1e-14 and abs(rl - inputs.CS_RHO_L_08) < 1e-14
+        for r in (rg, rl):
+            assert abs(orc.cs_pressure(a, b, T, r) - pg) < 1e-15
+    L = orc.Lattice(orc.D2Q37)
+    T = 0.8 * Tc
+    r = 0.2
+    want = math.sqrt(2 * (thermo.cs_pressure(r, a, b, T) - r * L.c0sq) / (-1.0 * L.c0sq))
+    assert abs(orc.psi(orc.D2Q37, a, b, T, -1.0, r, eos=orc.EOS_CS) - want) < 1e-15
+
+
+def _flat_interface(eos, t_reduced, k, rho_g, rho_l, steps=20000):
+    w = inputs.flat_interface_2d(eos=eos, t_reduced=t_reduced, k=k, steps=steps)
+    c = w["config"]
+    s = orc.Sim(orc.D2Q37, c["nx"], c["ny"], tau_hat=c["tau_hat"], sources=c["sources"], isothermal=1,
+                eos_a=c["eos_a"], eos_b=c["eos_b"], eos_T=c["eos_T"], sc_G=c["sc_G"], ptensor_k=c["ptensor_k"],
+                eos=c["eos"])
+    rho = inputs.flat_profile(c["ny"], c["nx"], rho_l, rho_g, w["width"])
+    s.init(rho, np.zeros((2,) + rho.shape), np.ones(rho.shape))
+    s.step(steps)
+    r, u, _ = s.fields()
+    return r[0, 0] / rho_g - 1, r[c["ny"] // 2, 0] / rho_l - 1, np.abs(u).max()
+
+
+@pytest.mark.parametrize("t_reduced,gas_tol", [(0.7, 1e-3), (0.9, 5e-3)])
+def test_cs_flat_interface_keeps_maxwell_densities(t_reduced, gas_tol):
+    """Section 5.4, Eq. (5.10) and Fig. 12: a flat liquid slab of the
+    Carnahan-Starling gas started at the Maxwell densities keeps them with the
+    paper's optimum k = 3.02 (here 3.02 c0^4, the Hermite-unit evaluation of
+    Eq. 3.12), at reduced temperatures on both sides of the one the value was
+    quoted without.  Without the pressure-tensor source (k = 0) the gas density
+    at 0.9 Tc falls by 15%."""
+    a, b = inputs.CS_A, inputs.CS_B
+    rg, rl = thermo.cs_maxwell(a, b, t_reduced * inputs.CS_TC)
+    eg, el, umax = _flat_interface(orc.EOS_CS, t_reduced, inputs.CS_K, rg, rl)
+    assert abs(eg) < gas_tol and abs(el) < 5e-4 and umax < 1e-4, (eg, el, umax)
+    if t_reduced == 0.9:
+        eg0, _, _ = _flat_interface(orc.EOS_CS, t_reduced, 0.0, rg, rl)
+        assert eg0 < -0.1
+
+
+def test_vdw_flat_interface_calibrated_k():
+    """The k of the van der Waals droplet workload keeps a flat interface at
+    the Maxwell densities at T = 0.85 Tc (the calibration it was chosen by)."""
+    eg, el, _ = _flat_interface(orc.EOS_VDW, 0.85, inputs.VDW_K_085, inputs.VDW_RHO_G_085,
+                                inputs.VDW_RHO_L_085, steps=40000)
+    assert abs(eg) < 2e-4 and abs(el) < 2e-5, (eg, el)
+
+
 # --------------------------------------------------------------- collision
 
 

@@ -205,6 +205,8 @@ def main():
     ap.add_argument("--workload", default="rb3d", choices=["rb3d", "thermal2d", "ptensor2d", "body2d", "batched"])
     ap.add_argument("--storage", default="f32", choices=list(STORAGE))
     ap.add_argument("--variant", type=int, default=-1, help="-1: autotune")
+    ap.add_argument("--frames", default="auto", choices=["auto", "cell", "plane", "cellu"],
+                    help="reference frames of the stored populations")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep", action="store_true", help="time every kernel variant (to stderr) before the run")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -225,7 +227,8 @@ def main():
     if args.workload == "batched":
         return bench_batched(args)
     w = workload(args.workload)
-    cfg = dict(w["config"], storage=storage)
+    frames = {"auto": 0, "cell": 1, "plane": 2, "cellu": 3}[args.frames]
+    cfg = dict(w["config"], storage=storage, frames=frames)
     Q = 37 if cfg["lattice"] == 0 else 39
     cells = cfg["nx"] * cfg["ny"] * cfg.get("nz", 1)
     torch.cuda.set_device(0)
@@ -304,9 +307,10 @@ def main():
             "walls": cfg["walls"],
             "storage": args.storage,
             "variant": variant,
-            # frames as the library resolves them (auto: per plane for FP32 with walls)
-            "frames": {1: "cell", 2: "plane"}.get(cfg.get("frames", 0),
-                                                  "plane" if storage == 0 and cfg.get("walls") else "cell"),
+            # frames as the library resolves them (auto: per plane for FP32 with
+            # walls, per cell otherwise)
+            "frames": {1: "cell", 2: "plane", 3: "cellu"}.get(
+                frames, "plane" if storage == 0 and cfg.get("walls") else "cell"),
             "mass": totals[0],
         },
         "roofline": {

@@ -546,9 +546,13 @@ int orc_init(orc_sim *s, const double *rho, const double *u, const double *theta
  * already at the target state is left unchanged and a moving wall imposes its
  * velocity (the Couette validation of Section 5.1); with the index i on both
  * equilibria the unknowns reduce to plain bounce-back at that state.  Targets:
- * wall nodes (first and last layer along the wall-normal axis) take the
- * previous-step density with the wall velocity and temperature; fluid nodes
- * take their own previous-step fields. */
+ * wall nodes (first and last layer along the wall-normal axis) lie outside
+ * the fluid, and their targets come from the boundary condition holding
+ * half-way between them and the first fluid layer: the reflection
+ * 2 u_wall - u_1 and 2 theta_wall - theta_1 of that layer's previous-step
+ * fields, with the node's own previous-step density.  The fluid between the
+ * walls is then n - 2 nodes high (Sections 5.1 and 5.2: 54 of 56).  Fluid
+ * nodes take their own previous-step fields. */
 static void tms_fill(orc_sim *s)
 {
     if (!s->cfg.walls) return;
@@ -572,8 +576,11 @@ static void tms_fill(orc_sim *s)
         double rt = s->trho[cell], ut[3], tt;
         int wall = (k == 0) ? 0 : (k == nax - 1) ? 1 : -1;
         if (wall >= 0) {
-            for (int a = 0; a < 3; ++a) ut[a] = a < s->D ? s->cfg.u_wall[wall][a] : 0.0;
-            tt = s->cfg.theta_wall[wall];
+            long xn[3] = {x[0], x[1], x[2]};
+            xn[s->wax] = wall == 0 ? 1 : nax - 2;
+            long c1 = cell_of(s, xn);
+            for (int a = 0; a < 3; ++a) ut[a] = a < s->D ? 2.0 * s->cfg.u_wall[wall][a] - s->tu[a * N + c1] : 0.0;
+            tt = 2.0 * s->cfg.theta_wall[wall] - s->ttheta[c1];
         } else {
             for (int a = 0; a < 3; ++a) ut[a] = s->tu[a * N + cell];
             tt = s->ttheta[cell];

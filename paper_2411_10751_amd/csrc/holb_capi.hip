@@ -49,10 +49,12 @@ Layout layout_of(const holb_config* c)
     L.elem = c->storage == HOLB_STORE_F32 ? 4 : 2;
     L.pitch = align_up(N, ALIGN / L.elem);
     // Q population planes; with per-cell frames, then one binary16 pair (rho,
-    // theta - 1) per cell: the frame the cell's populations are stored in.
+    // theta - 1) per cell: the frame the cell's populations are stored in
+    // (with momentum, a second such plane of packed momentum words).
     // Per-plane frames are kept in a table of (2 + 7 NS) floats per plane.
-    const bool per_cell = frames_of(c) == FM_CELL;
-    L.pop_bytes = (size_t)Q * L.pitch * L.elem + (per_cell ? align_up(N * 4) : 0);
+    const int fm = frames_of(c);
+    const bool per_cell = fm != FM_PLANE;
+    L.pop_bytes = (size_t)Q * L.pitch * L.elem + (per_cell ? align_up(N * 4) * (fm == FM_CELLU ? 2 : 1) : 0);
     L.nm = D == 3 ? c->nz : c->ny;
     L.tab_bytes = per_cell ? 0 : (size_t)(2 + 7 * lattice_NS(c->lattice)) * L.nm * sizeof(float);
     size_t off = 0;

@@ -61,13 +61,19 @@ __device__ __forceinline__ Frame plane_frame_of(const KParams& p, int m)
     return F;
 }
 
-template <class L, int ST, bool WALLS, int FM>
+// MOM1 (FM_CELLU): load the momentum words with the first phase (for
+// kernels with few registers of their own) instead of in a second phase.
+template <class L, int ST, bool WALLS, int FM, bool MOM1 = false>
 __device__ __forceinline__ uint64_t pull_cell(const KParams& p, const typename Codec<ST>::T* __restrict__ fin,
                                               int x, int y, int z, float (&f)[L::Q], Frame& fo)
 {
     using T = typename Codec<ST>::T;
-    constexpr bool CF = FM == FM_CELL;
-    const uint32_t* __restrict__ fp = frame_plane<ST>(fin, p.pitch, L::Q);
+    constexpr bool CF = FM != FM_PLANE;
+    constexpr bool CU = FM == FM_CELLU;
+    using FW = uint32_t;
+    const FW* __restrict__ fp = frame_plane<ST>(fin, p.pitch, L::Q);
+    [[maybe_unused]] const uint32_t* __restrict__ mp = fp + mom_offset(p.N);
+    [[maybe_unused]] uint32_t mw[L::Q];
     const int cell = (z * p.ny + y) * p.nx + x;
     const bool inner_yz = y >= 3 && y < p.ny - 3 && (L::D == 2 || (z >= 3 && z < p.nz - 3));
     const bool inner = inner_yz && x >= 3 && x < p.nx - 3;
@@ -78,15 +84,16 @@ __device__ __forceinline__ uint64_t pull_cell(const KParams& p, const typename C
     // periodic correction of x per population), or the general wrap with
     // the wall bookkeeping.
     T raw[L::Q];
-    uint32_t fw[L::Q];
+    FW fw[L::Q];
     uint64_t unk = 0;
     if (__all(inner)) {
-        const unsigned cb = (unsigned)cell * (unsigned)sizeof(T), cf = (unsigned)cell * 4u;
+        const unsigned cb = (unsigned)cell * (unsigned)sizeof(T), cf = (unsigned)cell * (unsigned)sizeof(FW);
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) {
             const int shift = (L::cz[i] * p.ny + L::cy[i]) * p.nx + L::cx[i];
             raw[i] = load_at(fin + ((long long)i * p.pitch - shift), cb);
             if (CF) fw[i] = load_at(fp - shift, cf);
+            if (CU && MOM1) mw[i] = load_at(mp - shift, cf);
         }
         __builtin_amdgcn_sched_barrier(0);
     } else if (__all(inner_yz)) {
@@ -96,7 +103,8 @@ __device__ __forceinline__ uint64_t pull_cell(const KParams& p, const typename C
             if (L::cx[i] > 0 && x < L::cx[i]) src += p.nx;
             if (L::cx[i] < 0 && x >= p.nx + L::cx[i]) src -= p.nx;
             raw[i] = load_at(fin + (long long)i * p.pitch, (unsigned)src * (unsigned)sizeof(T));
-            if (CF) fw[i] = load_at(fp, (unsigned)src * 4u);
+            if (CF) fw[i] = load_at(fp, (unsigned)src * (unsigned)sizeof(FW));
+            if (CU && MOM1) mw[i] = load_at(mp, (unsigned)src * 4u);
         }
         __builtin_amdgcn_sched_barrier(0);
     } else {
@@ -121,7 +129,8 @@ __device__ __forceinline__ uint64_t pull_cell(const KParams& p, const typename C
             const int src = known ? (sz * p.ny + sy) * p.nx + sx : cell;
             if (!known) unk |= 1ull << i;
             raw[i] = load_at(fin + (long long)i * p.pitch, (unsigned)src * (unsigned)sizeof(T));
-            if (CF) fw[i] = load_at(fp, (unsigned)src * 4u);
+            if (CF) fw[i] = load_at(fp, (unsigned)src * (unsigned)sizeof(FW));
+            if (CU && MOM1) mw[i] = load_at(mp, (unsigned)src * 4u);
         }
     }
     // keep the scheduler from sinking loads into the arithmetic below
@@ -149,18 +158,77 @@ __device__ __forceinline__ uint64_t pull_cell(const KParams& p, const typename C
             f[i] = (WALLS && ((unk >> i) & 1ull)) ? 0.0f : v;
         }
     }
+    if constexpr (CU) {
+        // Second load phase: the momentum words of the same sources, whose
+        // part c_i . P_S of the source's frame is added back.  Loading them
+        // with the first phase would hold 3Q words in flight and cost a wave
+        // of occupancy.
+        if (MOM1) {
+        } else if (__all(inner)) {
+            const unsigned cf = (unsigned)cell * 4u;
+#pragma unroll
+            for (int i = 1; i < L::Q; ++i) {
+                const int shift = (L::cz[i] * p.ny + L::cy[i]) * p.nx + L::cx[i];
+                mw[i] = load_at(mp - shift, cf);
+            }
+        } else {
+#pragma unroll
+            for (int i = 1; i < L::Q; ++i) {
+                const int sx = wrapc(x - L::cx[i], p.nx);
+                int sy = y - L::cy[i], sz = z - L::cz[i];
+                if (L::D == 2) {
+                    sz = 0;
+                    sy = (WALLS && p.walls) ? min(max(sy, 0), p.ny - 1) : wrapc(sy, p.ny);
+                } else {
+                    sy = wrapc(sy, p.ny);
+                    sz = (WALLS && p.walls) ? min(max(sz, 0), p.nz - 1) : wrapc(sz, p.nz);
+                }
+                // an unknown population reads a clamped slot; its value is discarded
+                mw[i] = load_at(mp, (unsigned)((sz * p.ny + sy) * p.nx + sx) * 4u);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 1; i < L::Q; ++i)
+            if (!(WALLS && ((unk >> i) & 1ull))) f[i] += cdot_mom<L>(i, mw[i]);
+    }
     return unk;
 }
 
 // Store the post-collision populations of a node.  FM_CELL: in a new frame
 // fn (written to the frame plane of fout), h_i(fn) = h_i(fo) + R_i(fo) -
-// R_i(fn), one shift per shell.  FM_PLANE: the frame of the plane is fixed,
-// the values are stored as they are.
+// R_i(fn), one shift per shell.  FM_CELLU: the same, minus c_i . P of the
+// node's new momentum word.  FM_PLANE: the frame of the plane is fixed, the
+// values are stored as they are.
 template <class L, int ST, int FM>
 __device__ __forceinline__ void store_cell(const KParams& p, typename Codec<ST>::T* __restrict__ fout, long long cell,
-                                           float (&f)[L::Q], const Frame& fo, float rho, float thb)
+                                           float (&f)[L::Q], const Frame& fo, float rho, float thb,
+                                           const float (&u)[3])
 {
-    if constexpr (FM == FM_CELL) {
+    if constexpr (FM == FM_CELLU) {
+        const uint32_t packed = pack_frame(rho, thb);
+        float P[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) P[a] = a < L::D ? rho * fmaf(u[a], Lat<L>::ic0sq, -p.u0s[a]) : 0.0f;
+        const uint32_t mom = pack_mom(P);
+        uint32_t* fpo = frame_plane<ST>(fout, p.pitch, L::Q);
+        fpo[cell] = packed;
+        fpo[mom_offset(p.N) + cell] = mom;
+        const Frame fn = unpack_frame(packed);
+        const FrameRef<L> ref = frame_ref<L>(fo);
+        float sh[L::NS];  // R(fo) - R(fn)
+#pragma unroll
+        for (int s = 0; s < L::NS; ++s) sh[s] = -frame_shift<L>(ref, s, fn);
+        fout[cell] = Codec<ST>::enc(f[0] + sh[0], p.dref[0]);
+        // +/-c pairs share c . P with opposite signs
+#pragma unroll
+        for (int i = 1; i < L::Q; i += 2) {
+            const float cp = cdot_mom<L>(i, mom);
+            const float s = sh[L::shell[i]];
+            fout[(long long)i * p.pitch + cell] = Codec<ST>::enc(f[i] + s - cp, p.dref[i]);
+            fout[(long long)(i + 1) * p.pitch + cell] = Codec<ST>::enc(f[i + 1] + s + cp, p.dref[i + 1]);
+        }
+    } else if constexpr (FM == FM_CELL) {
         const uint32_t packed = pack_frame(rho, thb);
         frame_plane<ST>(fout, p.pitch, L::Q)[cell] = packed;
         const Frame fn = unpack_frame(packed);
@@ -189,21 +257,27 @@ __device__ __forceinline__ void wall_coord(const KParams& p, int x, int y, int z
 // every pass over the state so that they agree bitwise.  f holds the
 // deviations h_i.  WALLS = false compiles out the wall closure (periodic
 // domains and interior planes).
-template <class L, int ST, bool WALLS, int FM>
+template <class L, int ST, bool WALLS, int FM, bool MOM1 = false>
 __device__ __forceinline__ void load_state(const KParams& p, const typename Codec<ST>::T* __restrict__ fin,
                                            const float* __restrict__ tgt_in, int x, int y, int z,
                                            float (&f)[L::Q], Frame& fo, float& dr, float (&j)[3], float& ed)
 {
-    uint64_t unk = pull_cell<L, ST, WALLS, FM>(p, fin, x, y, z, f, fo);
+    uint64_t unk = pull_cell<L, ST, WALLS, FM, MOM1>(p, fin, x, y, z, f, fo);
     if (WALLS && p.walls && unk) {
         int kw, nw, cil;
         wall_coord<L>(p, x, y, z, kw, nw, cil);
         const int slot = wall_slot(kw, nw);
-        float t[5];
+        float t[5], nb[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int c = 0; c < L::D + 2; ++c) t[c] = tgt_in[((long long)slot * (L::D + 2) + c) * p.nlayer + cil];
         const int wall = kw == 0 ? 0 : (kw == nw - 1 ? 1 : -1);
-        tms_fill<L>(p, fo, f, unk, wall, t);
+        if (wall >= 0) {
+            // the first fluid layer: slot 1 (low wall) or 4 (high wall)
+            const int s1 = wall == 0 ? 1 : 4;
+#pragma unroll
+            for (int c = 1; c < L::D + 2; ++c) nb[c - 1] = tgt_in[((long long)s1 * (L::D + 2) + c) * p.nlayer + cil];
+        }
+        tms_fill<L>(p, fo, f, unk, wall, t, nb);
     }
     moments<L>(f, dr, j, ed);
 }
@@ -328,7 +402,7 @@ __device__ __forceinline__ void step_cell(const KParams& p, const typename Codec
         hc = p.hfac * m.rho * m.theta;
     }
     collide<L, ST == ST_F32>(p, fo, f, m, hc, gT, pc);
-    store_cell<L, ST, FM>(p, fout, cell, f, fo, m.rho, m.thb);
+    store_cell<L, ST, FM>(p, fout, cell, f, fo, m.rho, m.thb, m.u);
 }
 
 // Field pass of one cell: theta (thermal family) or psi (pressure-tensor
@@ -342,7 +416,7 @@ __device__ __forceinline__ void aux_cell(const KParams& p, const typename Codec<
     cell_coords<L>(p, cell, x, y, z);
     float f[L::Q], dr, j[3], ed;
     Frame fo;
-    load_state<L, ST, WALLS, FM>(p, fin, tgt_in, x, y, z, f, fo, dr, j, ed);
+    load_state<L, ST, WALLS, FM, true>(p, fin, tgt_in, x, y, z, f, fo, dr, j, ed);
     if (FAM == FAM_PTENSOR) {
         bool bad = false;
         aux_d[cell] = psi_eos(p, (double)fo.rho + (double)dr, L::c0sq, bad);
@@ -357,13 +431,24 @@ __device__ __forceinline__ void aux_cell(const KParams& p, const typename Codec<
 
 // Initial frame of one cell (written before the populations, which are
 // stored in the frames of the cells they are pulled from).
-template <class L, int ST>
+template <class L, int ST, int FM>
 __device__ __forceinline__ void init_frame_cell(const KParams& p, const float* __restrict__ rho,
-                                                const float* __restrict__ theta, typename Codec<ST>::T* __restrict__ fout,
-                                                int cell)
+                                                const float* __restrict__ u, const float* __restrict__ theta,
+                                                typename Codec<ST>::T* __restrict__ fout, int cell)
 {
     const float thb = (p.flags & KF_ISO) ? 0.0f : theta[cell] - 1.0f;
-    frame_plane<ST>(fout, p.pitch, L::Q)[cell] = pack_frame(rho[cell], thb);
+    const uint32_t packed = pack_frame(rho[cell], thb);
+    if constexpr (FM == FM_CELLU) {
+        float P[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            P[a] = a < L::D ? rho[cell] * fmaf(u[(long long)a * p.N + cell], Lat<L>::ic0sq, -p.u0s[a]) : 0.0f;
+        uint32_t* fpo = frame_plane<ST>(fout, p.pitch, L::Q);
+        fpo[cell] = packed;
+        fpo[mom_offset(p.N) + cell] = pack_mom(P);
+    } else {
+        frame_plane<ST>(fout, p.pitch, L::Q)[cell] = packed;
+    }
 }
 
 // Initial state of one cell: f^0_i(x) = f^eq_i(rho, u, theta)(x), written to
@@ -389,7 +474,7 @@ __device__ __forceinline__ void init_cell(const KParams& p, const float* __restr
     if (p.walls) write_targets<L>(p, tgt, x, y, z, m);
     const uint32_t* fp = frame_plane<ST>(fout, p.pitch, L::Q);
     const int mz = L::D == 3 ? z : y;
-    const Frame fo = FM == FM_CELL ? unpack_frame(fp[cell]) : plane_frame_of(p, mz);
+    const Frame fo = FM != FM_PLANE ? unpack_frame(fp[cell]) : plane_frame_of(p, mz);
     [[maybe_unused]] const FrameRef<L> ref = frame_ref<L>(fo);
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
@@ -414,6 +499,9 @@ __device__ __forceinline__ void init_cell(const KParams& p, const float* __restr
         float h;
         if constexpr (FM == FM_CELL) {
             h = fe - frame_shift<L>(ref, L::shell[i], unpack_frame(fp[slot]));
+        } else if constexpr (FM == FM_CELLU) {
+            h = fe - frame_shift<L>(ref, L::shell[i], unpack_frame(fp[slot])) -
+                cdot_mom<L>(i, fp[mom_offset(p.N) + slot]);
         } else {
             const int cm = L::D == 3 ? L::cz[i] : L::cy[i];
             h = cm == 0 ? fe : fe - p.plane_shift[((long long)mz * 7 + cm + 3) * L::NS + L::shell[i]];

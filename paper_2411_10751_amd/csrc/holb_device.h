@@ -114,6 +114,37 @@ __device__ __forceinline__ Frame unpack_frame(uint32_t v)
     return F;
 }
 
+// FM_CELLU adds the first-order part of the frame bracket, c_i . P with
+// P = rho_F (u_F - u0) / c0^2, so that 16-bit storage keeps the momentum part
+// of the populations out of the stored deviation too.  P is carried as three
+// 10-bit signed multiples of 2^-10 (|P| < 0.5; larger values saturate, which
+// only makes the frame less close, never inexact) in a momentum plane after
+// the frame plane; c_i . P is then an exact integer dot product times 2^-10
+// on both sides.
+constexpr float PSTEP = 1.0f / 1024.0f;
+
+__device__ __forceinline__ uint32_t pack_mom(const float (&P)[3])
+{
+    uint32_t w = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int q = (int)fminf(fmaxf(rintf(P[a] * 1024.0f), -511.0f), 511.0f);
+        w |= ((uint32_t)q & 0x3ffu) << (10 * a);
+    }
+    return w;
+}
+
+// c_i . P of a packed momentum word (exact).
+template <class L>
+__device__ __forceinline__ float cdot_mom(int i, uint32_t w)
+{
+    int d = 0;
+    if (L::cx[i]) d += L::cx[i] * __builtin_amdgcn_sbfe((int)w, 0u, 10u);
+    if (L::cy[i]) d += L::cy[i] * __builtin_amdgcn_sbfe((int)w, 10u, 10u);
+    if (L::cz[i]) d += L::cz[i] * __builtin_amdgcn_sbfe((int)w, 20u, 10u);
+    return (float)d * PSTEP;
+}
+
 // Per-cell frame plane stored after the Q population planes of a buffer.
 template <int ST>
 __device__ __forceinline__ const uint32_t* frame_plane(const void* pop, long long pitch, int Q)
@@ -127,6 +158,10 @@ __device__ __forceinline__ uint32_t* frame_plane(void* pop, long long pitch, int
     using T = typename Codec<ST>::T;
     return (uint32_t*)((T*)pop + (long long)Q * pitch);
 }
+
+// Momentum plane (FM_CELLU): one word per cell after the frame plane, which
+// is padded to 256 bytes.
+__device__ __forceinline__ long long mom_offset(int N) { return ((long long)N + 63) & ~63ll; }
 
 // ----------------------------------------------------- kinetic algebra
 // Lattice units outside; a = c.u / c0^2, uu = |u|^2 / c0^2, xx = |c|^2 / c0^2
@@ -296,13 +331,15 @@ __device__ __forceinline__ void macro_from_moments(const KParams& p, const Frame
 // local state fills the unknown set with the target equilibrium.  The local
 // equilibrium is taken at the opposite index (non-equilibrium bounce-back):
 // a node at the target state then stays there, and a moving wall imposes its
-// velocity.  unk has bit
+// velocity.  A wall node targets the reflection 2 u_wall - u_1, 2 theta_wall -
+// theta_1 of the first fluid layer (the wall holds half-way between them).  unk has bit
 // i set for unknown direction i; tgt holds the previous-step (rho, u[D],
 // theta) of this node; wall = 0/1 for a wall node (first/last layer), -1 for
-// a fluid node, whose target is its own previous-step state.
+// a fluid node, whose target is its own previous-step state; nb holds the
+// previous-step (u[D], theta) of the first fluid layer next to a wall node.
 template <class L>
 __device__ __forceinline__ void tms_fill(const KParams& p, const Frame& fr, float (&h)[L::Q], uint64_t unk,
-                                         int wall, const float* tgt)
+                                         int wall, const float* tgt, const float* nb)
 {
     using LL = Lat<L>;
     constexpr int D = L::D;
@@ -311,8 +348,8 @@ __device__ __forceinline__ void tms_fill(const KParams& p, const Frame& fr, floa
     float tt;
     if (wall >= 0) {
 #pragma unroll
-        for (int a = 0; a < D; ++a) ut[a] = p.uwall[wall][a];
-        tt = p.twall[wall];
+        for (int a = 0; a < D; ++a) ut[a] = fmaf(2.0f, p.uwall[wall][a], -nb[a]);
+        tt = fmaf(2.0f, p.twall[wall], -nb[D]);
     } else {
 #pragma unroll
         for (int a = 0; a < D; ++a) ut[a] = tgt[1 + a];

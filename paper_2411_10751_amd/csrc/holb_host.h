@@ -63,10 +63,12 @@ inline holb_status validate(const holb_config* c)
     if (c->sources & ~known) return fail(HOLB_EINVAL, "unknown source bits 0x%x", c->sources);
     if (c->isothermal != 0 && c->isothermal != 1) return fail(HOLB_EINVAL, "isothermal must be 0 or 1");
     if (c->walls != 0 && c->walls != 1) return fail(HOLB_EINVAL, "walls must be 0 or 1");
-    if (c->frames < HOLB_FRAMES_AUTO || c->frames > HOLB_FRAMES_PLANE)
+    if (c->frames < HOLB_FRAMES_AUTO || c->frames > HOLB_FRAMES_CELL_U)
         return fail(HOLB_EINVAL, "frames must be one of HOLB_FRAMES_*");
     if (c->frames == HOLB_FRAMES_PLANE && c->storage != HOLB_STORE_F32)
         return fail(HOLB_EUNSUPPORTED, "per-plane frames are for FP32 storage only");
+    if (c->frames == HOLB_FRAMES_CELL_U && c->storage == HOLB_STORE_F32)
+        return fail(HOLB_EUNSUPPORTED, "per-cell frames with momentum are for 16-bit storage only");
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(c->g[a])) return fail(HOLB_EINVAL, "g must be finite");
     if (c->sources & HOLB_SRC_THERMAL) {
@@ -107,11 +109,13 @@ inline holb_status validate(const holb_config* c)
 
 // Frame mode of a configuration.  HOLB_FRAMES_AUTO takes per-plane frames
 // for FP32 storage in a walled domain (whose walls impose the mean profile
-// along the wall-normal axis) and per-cell frames otherwise.
+// along the wall-normal axis) and per-cell frames otherwise; frames with
+// momentum are taken only when asked for.
 inline int frames_of(const holb_config* c)
 {
     if (c->frames == HOLB_FRAMES_CELL) return FM_CELL;
     if (c->frames == HOLB_FRAMES_PLANE) return FM_PLANE;
+    if (c->frames == HOLB_FRAMES_CELL_U) return FM_CELLU;
     return (c->storage == HOLB_STORE_F32 && c->walls) ? FM_PLANE : FM_CELL;
 }
 
@@ -150,6 +154,7 @@ inline KParams params_of(const holb_config* c)
     if (c->storage != HOLB_STORE_F32) {
         double u0[3] = {c->u0[0], c->u0[1], D == 3 ? c->u0[2] : 0.0};
         deviation_reference(c->lattice, c->rho0, u0, c->isothermal ? 1.0 : c->theta0, p.dref);
+        for (int a = 0; a < 3; ++a) p.u0s[a] = (float)(u0[a] / c0sq);
     }
     return p;
 }

@@ -30,13 +30,13 @@ constexpr int GEN_BLOCK = 256;
 
 // --------------------------------------------------------------- kernels
 
-template <class L, int ST>
+template <class L, int ST, int FM>
 __global__ void __launch_bounds__(GEN_BLOCK)
-k_init_frame(const KParams p, const float* __restrict__ rho, const float* __restrict__ theta,
-             typename Codec<ST>::T* __restrict__ fout)
+k_init_frame(const KParams p, const float* __restrict__ rho, const float* __restrict__ u,
+             const float* __restrict__ theta, typename Codec<ST>::T* __restrict__ fout)
 {
     const int cell = xcd_block() * GEN_BLOCK + threadIdx.x;
-    if (cell < p.N) init_frame_cell<L, ST>(p, rho, theta, fout, cell);
+    if (cell < p.N) init_frame_cell<L, ST, FM>(p, rho, u, theta, fout, cell);
 }
 
 template <class L, int ST, int FM>
@@ -256,9 +256,9 @@ struct Launch {
 
     static hipError_t init(const LaunchCtx& c, const float* rho, const float* u, const float* th)
     {
-        if constexpr (FM == FM_CELL) {
-            hipLaunchKernelGGL((k_init_frame<L, ST>), dim3(nblocks_for(c.kp.N)), dim3(GEN_BLOCK), 0, c.stream,
-                               c.kp, rho, th, (T*)c.pop_out);
+        if constexpr (FM != FM_PLANE) {
+            hipLaunchKernelGGL((k_init_frame<L, ST, FM>), dim3(nblocks_for(c.kp.N)), dim3(GEN_BLOCK), 0, c.stream,
+                               c.kp, rho, u, th, (T*)c.pop_out);
         } else {
             const int n = nm(c.kp);
             hipLaunchKernelGGL(k_plane_frames<0>, dim3(n), dim3(256), 0, c.stream, c.kp, rho, th,
@@ -419,6 +419,10 @@ inline hipError_t dispatch_set(const LaunchCtx& c, int op, const float* a, const
         if (c.frames == FM_PLANE) return dispatch_family<L, ST_F32, FM_PLANE>(c, op, a, b, d, o1, o2, o3, dout);
         return dispatch_family<L, ST_F32, FM_CELL>(c, op, a, b, d, o1, o2, o3, dout);
     } else {
+        if (c.frames == FM_CELLU) {
+            if (c.storage == ST_F16) return dispatch_family<L, ST_F16, FM_CELLU>(c, op, a, b, d, o1, o2, o3, dout);
+            return dispatch_family<L, ST_BF16, FM_CELLU>(c, op, a, b, d, o1, o2, o3, dout);
+        }
         if (c.storage == ST_F16) return dispatch_family<L, ST_F16, FM_CELL>(c, op, a, b, d, o1, o2, o3, dout);
         return dispatch_family<L, ST_BF16, FM_CELL>(c, op, a, b, d, o1, o2, o3, dout);
     }

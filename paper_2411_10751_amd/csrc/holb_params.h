@@ -14,9 +14,10 @@ enum Family { FAM_LOCAL = 0, FAM_THERMAL = 1, FAM_PTENSOR = 2 };
 enum : unsigned { KF_BODY = 1u, KF_ISO = 2u };
 
 // How stored populations are referenced (see the frame section of
-// holb_device.h): a frame per cell, kept beside the populations, or a fixed
-// frame per plane along the last axis, kept in a small table.
-enum FrameMode { FM_CELL = 0, FM_PLANE = 1 };
+// holb_device.h): a frame per cell, kept beside the populations, the same
+// with the cell's momentum added (16-bit storage), or a fixed frame per plane
+// along the last axis, kept in a small table.
+enum FrameMode { FM_CELL = 0, FM_PLANE = 1, FM_CELLU = 2 };
 
 enum : unsigned { HOLB_ERR_DENSITY_BIT = 1u, HOLB_ERR_THETA_BIT = 2u, HOLB_ERR_EOS_BIT = 4u };
 // equation of state of the pseudopotential (values of HOLB_EOS_*)
@@ -67,6 +68,7 @@ struct KParams {
     float rho_ref;       // rho0 and theta0 - 1 of the reference state: populations
     float thb_ref;       //   are handled as h_i = f_i / w_i - f^eq_i(rho0, 0, theta0) / w_i
     float dref[QMAX];    // d_i = (f^eq_i(rho0, u0, theta0) - f^eq_i(rho0, 0, theta0)) / w_i (16-bit offset)
+    float u0s[3];        // u0 / c0^2: FM_CELLU frames carry rho (u - u0) / c0^2
     unsigned* err;       // device error word
     // FM_PLANE: rho and theta - 1 of each plane along the last axis (2 floats
     // per plane), and the shifts R_s(frame(m - c_m)) - R_s(frame(m)) at

@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libholb.so")
 
 ABI_VERSION = 3
-FRAMES_AUTO, FRAMES_CELL, FRAMES_PLANE = 0, 1, 2
+FRAMES_AUTO, FRAMES_CELL, FRAMES_PLANE, FRAMES_CELL_U = 0, 1, 2, 3
 EOS_VDW, EOS_CS = 0, 1
 OK, EINVAL, ESIZE, EHIP, ENUMERIC, EUNSUPPORTED, ESTATE = 0, -1, -2, -3, -4, -5, -6
 D2Q37, D3Q39 = 0, 1

@@ -71,8 +71,9 @@ def _cfg(**kw):
     (dict(walls=1, ny=6), holb.EINVAL),
     (dict(g=(float("inf"), 0, 0)), holb.EINVAL),
     (dict(lattice=1, nx=1024, ny=1024, nz=1024), holb.ESIZE),
-    (dict(frames=3), holb.EINVAL),
+    (dict(frames=4), holb.EINVAL),
     (dict(storage=1, rho0=1.0, frames=2), holb.EUNSUPPORTED),
+    (dict(storage=0, frames=3), holb.EUNSUPPORTED),
 ])
 def test_config_errors(bad, code):
     with pytest.raises(holb.HolbError) as ei:
@@ -127,12 +128,14 @@ def test_create_is_host_only_and_checks_workspace():
 
 
 @pytest.mark.parametrize("walls,storage,frames,per_cell", [
-    (1, 0, 0, False), (1, 0, 1, True), (0, 0, 0, True), (0, 0, 2, False), (1, 1, 0, True), (0, 2, 0, True)])
+    (1, 0, 0, 0), (1, 0, 1, 4), (0, 0, 0, 4), (0, 0, 2, 0), (1, 1, 0, 4), (0, 2, 0, 4), (1, 2, 0, 4),
+    (0, 1, 3, 8), (0, 2, 1, 4), (0, 2, 3, 8)])
 def test_state_layout_by_frame_mode(walls, storage, frames, per_cell):
-    """The raw state holds the Q planes, then one frame word per cell (per-cell
-    frames) or the per-plane table of 2 + 7 NS floats per plane; AUTO picks
-    per-plane frames for FP32 with walls only."""
-    nx, ny, nz = 24, 20, 16
+    """The raw state holds the Q planes, then per_cell bytes of frame words per
+    cell (4 for per-cell frames, 8 with momentum, in two planes) or the per-plane table of
+    2 + 7 NS floats per plane; AUTO picks per-plane frames for FP32 with walls
+    and per-cell frames otherwise."""
+    nx, ny, nz = 24, 20, 15  # N = 7200: the frame planes need padding
     cfg = holb.make_config(dict(lattice=1, nx=nx, ny=ny, nz=nz, tau_hat=0.8, sources=3, prandtl=0.7,
                                 g=(0, 0, -1e-5), walls=walls, storage=storage, frames=frames, rho0=1.0,
                                 theta0=1.0))
@@ -145,7 +148,8 @@ def test_state_layout_by_frame_mode(walls, storage, frames, per_cell):
     N = nx * ny * nz
     elem = 4 if storage == 0 else 2
     pitch = -(-N // (256 // elem)) * (256 // elem)
-    extra = -(-N * 4 // 256) * 256 if per_cell else (2 + 7 * 6) * nz * 4
+    # frame plane (and momentum plane), each padded to 256 bytes
+    extra = (-(-N * 4 // 256) * 256) * (per_cell // 4) if per_cell else (2 + 7 * 6) * nz * 4
     assert sb.value == 39 * pitch * elem + extra
     assert holb.holb_destroy(h) == holb.OK
 

@@ -310,6 +310,29 @@ def test_full_thermal_1024_windows():
     assert max(worst) <= TOL[0], worst
 
 
+@pytest.mark.parametrize("storage,frames", [(0, 0), pytest.param(1, 0, marks=pytest.mark.xfail(
+    reason="FP16 with per-cell frames reaches u 3.7e-3 after 20,000 steps, against the 2e-3 bound", strict=False)),
+    (1, 3), pytest.param(2, 3, marks=pytest.mark.xfail(
+        reason="BF16 keeps 8 significand bits: even with momentum frames u reaches 4.6e-2 after 20,000 steps",
+        strict=False))])
+def test_full_thermal_1024_full_horizon(storage, frames):
+    """The 1024^2 thermal workload over its whole 20,000-step horizon, in the
+    launch configuration the benchmark times.  Its fields vary along x only,
+    so every row of the exact solution is the same: the FP64 oracle runs one
+    1024 x 1 row (periodic in y, the same scheme) and every GPU row is
+    compared with it.  The workload is quoted on FP32 (u 7.8e-6 at 20,000
+    steps); FP16 needs momentum frames over this horizon (u 1.8e-3, against
+    3.7e-3 with per-cell frames)."""
+    w = inputs.thermal_2d(n=1024, steps=20000)
+    n, steps = 1024, w["steps"]
+    log("case %s full size, full horizon, storage %d frames %d" % (w["name"], storage, frames))
+    g = run_gpu(dict(w["config"], frames=frames), w["rho"], w["u"], w["theta"], steps, storage=storage, tune=True)
+    row = dict(w["config"], ny=1)
+    o = run_oracle(row, w["rho"][:1], w["u"][:, :1], w["theta"][:1], steps, shape=(1, n))
+    ob = (np.broadcast_to(o[0], (n, n)), np.broadcast_to(o[1], (2, n, n)), np.broadcast_to(o[2], (n, n)))
+    assert_parity(g, ob, 0, TOL[storage], w["name"] + " 20k steps st%d fr%d" % (storage, frames))
+
+
 # --------------------------------------------------- reductions and state
 
 
@@ -459,22 +482,24 @@ def test_codec_round_to_nearest_even(storage, frames):
 
 
 def test_batched_parity_and_self_consistency():
-    """16 random runs of the batched workload: each matches the oracle, and
-    each is bitwise equal to the same run launched alone."""
+    """16 random runs of the batched workload over its 200-step horizon: each
+    matches the oracle, and each is bitwise equal to the same run launched
+    alone."""
     import torch
     from paper_2411_10751_amd import holb
-    runs = inputs.batched_runs(nruns=16, nmin=32, nmax=80, steps=60)
-    log("case batched 16 runs")
+    runs = inputs.batched_runs(nruns=16, nmin=32, nmax=80, steps=200)
+    steps = runs[0]["steps"]
+    log("case batched 16 runs, %d steps" % steps)
     b = holb.Batch([r["config"] for r in runs])
     b.init([r["rho"] for r in runs], [r["u"] for r in runs], [r["theta"] for r in runs])
-    b.step(60)
+    b.step(steps)
     for k, r in enumerate(runs):
         gf = [x.cpu().numpy().astype(np.float64) for x in b.fields(k)]
-        o = run_oracle(r["config"], r["rho"], r["u"], r["theta"], 60)
+        o = run_oracle(r["config"], r["rho"], r["u"], r["theta"], steps)
         assert_parity(gf, o, 0, TOL[0], r["name"])
         if k < 3:
             # batched runs keep per-plane frames: the same run alone, same frames
-            alone = run_gpu(dict(r["config"], frames=2), r["rho"], r["u"], r["theta"], 60)
+            alone = run_gpu(dict(r["config"], frames=2), r["rho"], r["u"], r["theta"], steps)
             for a, bb in zip(gf, alone):
                 assert np.array_equal(a, bb)
     torch.cuda.synchronize()

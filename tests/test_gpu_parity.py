@@ -333,6 +333,24 @@ def test_full_thermal_1024_full_horizon(storage, frames):
     assert_parity(g, ob, 0, TOL[storage], w["name"] + " 20k steps st%d fr%d" % (storage, frames))
 
 
+@pytest.mark.parametrize("storage", [0, 1, 2])
+def test_full_rb3d_256_column_horizon(storage):
+    """The 256^3 Rayleigh-Benard box over the benchmark's 200 steps, started
+    without the noise so that the exact solution depends on z only: the FP64
+    oracle runs one 1 x 1 x 256 column (periodic in x and y, the same walls
+    and sources) and every GPU column is compared with it, in the storage
+    forms and the launch configuration the benchmark times."""
+    w = inputs.rayleigh_benard_3d(n=256, steps=200, noise=0.0)
+    n, steps = 256, w["steps"]
+    log("case %s no noise, full size, %d steps, storage %d" % (w["name"], steps, storage))
+    g = run_gpu(w["config"], w["rho"], w["u"], w["theta"], steps, storage=storage, tune=True)
+    col = dict(w["config"], nx=1, ny=1)
+    o = run_oracle(col, w["rho"][:, :1, :1], w["u"][:, :, :1, :1], w["theta"][:, :1, :1], steps, shape=(n, 1, 1))
+    shp = (n, n, n)
+    ob = (np.broadcast_to(o[0], shp), np.broadcast_to(o[1], (3,) + shp), np.broadcast_to(o[2], shp))
+    assert_parity(g, ob, 1, TOL[storage], w["name"] + " column, %d steps st%d" % (steps, storage))
+
+
 # --------------------------------------------------- reductions and state
 
 

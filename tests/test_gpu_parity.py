@@ -351,6 +351,29 @@ def test_full_rb3d_256_column_horizon(storage):
     assert_parity(g, ob, 1, TOL[storage], w["name"] + " column, %d steps st%d" % (steps, storage))
 
 
+@pytest.mark.parametrize("storage", [0, pytest.param(1, marks=pytest.mark.xfail(
+    reason="FP16: u reaches 2.5e-3 at the interfaces after 1000 steps (2e-5 in absolute terms, relative to "
+           "the 0.01 c0 floor of the velocity scale), against the 2e-3 bound; rho 1.3e-3 passes", strict=False))])
+def test_full_ptensor_2048_slab_horizon(storage):
+    """The pressure-tensor workload's gas (van der Waals, 0.85 Tc, its k) on the
+    full 2048^2 grid over its 1000-step horizon, as a flat liquid slab
+    (Eq. 5.10) that depends on y only: every GPU column is compared with the
+    FP64 oracle's 1 x 2048 column, in FP32 and in FP16 (the storage the
+    droplet workload is quoted on)."""
+    n, steps = 2048, 1000
+    w = inputs.flat_interface_2d(ny=n, nx=n, eos=inputs.EOS_VDW, t_reduced=0.85, steps=steps)
+    cfg = dict(w["config"], rho0=float((inputs.VDW_RHO_L_085 + inputs.VDW_RHO_G_085) / 2))
+    rho = inputs.flat_profile(n, n, inputs.VDW_RHO_L_085, inputs.VDW_RHO_G_085, w["width"]).astype(np.float32)
+    u = np.zeros((2, n, n), np.float32)
+    th = np.ones((n, n), np.float32)
+    log("case vdW slab %d^2, %d steps, storage %d" % (n, steps, storage))
+    g = run_gpu(cfg, rho, u, th, steps, storage=storage, tune=True)
+    col = dict(cfg, nx=1)
+    o = run_oracle(col, rho[:, :1], u[:, :, :1], th[:, :1], steps, shape=(n, 1))
+    ob = (np.broadcast_to(o[0], (n, n)), np.broadcast_to(o[1], (2, n, n)), np.broadcast_to(o[2], (n, n)))
+    assert_parity(g, ob, 0, TOL[storage], "vdW slab 2048^2, %d steps st%d" % (steps, storage))
+
+
 # --------------------------------------------------- reductions and state
 
 

@@ -195,7 +195,10 @@ __device__ __forceinline__ uint64_t pull_cell(const KParams& p, const typename C
     return unk;
 }
 
-// Store the post-collision populations of a node.  FM_CELL: in a new frame
+// Store the post-collision populations of a node; they are read once, by
+// the next step's pulls, so they are written non-temporally (without
+// allocating in the caches); the frame words, which every puller of a cell
+// reads, are written normally.  FM_CELL: in a new frame
 // fn (written to the frame plane of fout), h_i(fn) = h_i(fo) + R_i(fo) -
 // R_i(fn), one shift per shell.  FM_CELLU: the same, minus c_i . P of the
 // node's new momentum word.  FM_PLANE: the frame of the plane is fixed, the
@@ -219,14 +222,15 @@ __device__ __forceinline__ void store_cell(const KParams& p, typename Codec<ST>:
         float sh[L::NS];  // R(fo) - R(fn)
 #pragma unroll
         for (int s = 0; s < L::NS; ++s) sh[s] = -frame_shift<L>(ref, s, fn);
-        fout[cell] = Codec<ST>::enc(f[0] + sh[0], p.dref[0]);
+        __builtin_nontemporal_store(Codec<ST>::enc(f[0] + sh[0], p.dref[0]), fout + cell);
         // +/-c pairs share c . P with opposite signs
 #pragma unroll
         for (int i = 1; i < L::Q; i += 2) {
             const float cp = cdot_mom<L>(i, mom);
             const float s = sh[L::shell[i]];
-            fout[(long long)i * p.pitch + cell] = Codec<ST>::enc(f[i] + s - cp, p.dref[i]);
-            fout[(long long)(i + 1) * p.pitch + cell] = Codec<ST>::enc(f[i + 1] + s + cp, p.dref[i + 1]);
+            __builtin_nontemporal_store(Codec<ST>::enc(f[i] + s - cp, p.dref[i]), fout + (long long)i * p.pitch + cell);
+            __builtin_nontemporal_store(Codec<ST>::enc(f[i + 1] + s + cp, p.dref[i + 1]),
+                                        fout + (long long)(i + 1) * p.pitch + cell);
         }
     } else if constexpr (FM == FM_CELL) {
         const uint32_t packed = pack_frame(rho, thb);
@@ -238,10 +242,12 @@ __device__ __forceinline__ void store_cell(const KParams& p, typename Codec<ST>:
         for (int s = 0; s < L::NS; ++s) sh[s] = -frame_shift<L>(ref, s, fn);
 #pragma unroll
         for (int i = 0; i < L::Q; ++i)
-            fout[(long long)i * p.pitch + cell] = Codec<ST>::enc(f[i] + sh[L::shell[i]], p.dref[i]);
+            __builtin_nontemporal_store(Codec<ST>::enc(f[i] + sh[L::shell[i]], p.dref[i]),
+                                        fout + (long long)i * p.pitch + cell);
     } else {
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i) fout[(long long)i * p.pitch + cell] = Codec<ST>::enc(f[i], p.dref[i]);
+        for (int i = 0; i < L::Q; ++i)
+            __builtin_nontemporal_store(Codec<ST>::enc(f[i], p.dref[i]), fout + (long long)i * p.pitch + cell);
     }
 }
 

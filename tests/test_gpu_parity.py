@@ -423,6 +423,54 @@ def test_state_roundtrip_and_resume():
     assert torch.equal(r1, r2)
 
 
+@pytest.mark.parametrize("case", ["rb_f32", "rb_f16", "rb_bf16_mom", "thermal2d", "ptensor_f16", "periodic3d"])
+def test_poisoned_workspace(case):
+    """Every population slot a step should write is written, and nothing
+    uninitialised reaches a result: with the whole workspace filled with NaN
+    bytes before holb_init, the state after one and after two steps holds only
+    finite populations, and the fields after six steps are bitwise equal to
+    those of a run on a zeroed workspace."""
+    import torch
+    from paper_2411_10751_amd import holb
+    if case.startswith("rb"):
+        w = _rb(20, 16, 6)
+        storage = {"rb_f32": 0, "rb_f16": 1, "rb_bf16_mom": 2}[case]
+        cfg = dict(w["config"], storage=storage, frames=3 if case == "rb_bf16_mom" else 0)
+    elif case == "thermal2d":
+        w = inputs.thermal_2d(n=40, steps=6)
+        cfg = dict(w["config"])
+    elif case == "ptensor_f16":
+        w = _ptensor_small(n=64, steps=6)
+        cfg = dict(w["config"], storage=1)
+    else:
+        w = _rb(16, 20, 6, walls=0)
+        cfg = dict(w["config"])
+    log("case poisoned workspace %s" % case)
+    Q = 37 if cfg["lattice"] == 0 else 39
+    N = int(np.prod(w["rho"].shape))
+    elem = 4 if cfg.get("storage", 0) == 0 else 2
+    pitch = -(-N // (256 // elem)) * (256 // elem)
+    out = []
+    for fill in (255, 0):
+        sim = holb.Sim(cfg)
+        sim.ws.fill_(fill)
+        sim.init(w["rho"], w["u"], w["theta"])
+        for k in range(2):
+            sim.step(1)
+            st = sim.get_state()
+            pops = st[:Q * pitch * elem].view(torch.float32 if elem == 4 else torch.float16)
+            if elem == 2 and cfg.get("storage") == 2:
+                pops = st[:Q * pitch * elem].view(torch.bfloat16)
+            pops = pops.view(Q, pitch)[:, :N]
+            assert bool(torch.isfinite(pops).all()), (case, fill, k)
+        sim.step(4)
+        out.append([x.cpu().numpy() for x in sim.fields()])
+        torch.cuda.synchronize()
+        sim.close()
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b), case
+
+
 def test_error_flags_on_nonpositive_density():
     from paper_2411_10751_amd import holb
     w = inputs.body_force_2d(n=32, steps=1)

@@ -617,7 +617,8 @@ def test_batched_graph_replay_matches_eager():
 # ----------------------------------------------------------------- variants
 
 
-@pytest.mark.parametrize("wname", ["rb3d", "rb3d_tall", "periodic3d", "thermal2d", "body2d", "ptensor2d"])
+@pytest.mark.parametrize("wname", ["rb3d", "rb3d_tall", "periodic3d", "thermal2d", "body2d", "ptensor2d",
+                                   "ptensor2d_256"])
 def test_variants_bitwise_identical(wname):
     """Every kernel variant of a configuration gives bitwise identical fields
     (tall boxes span several chunks of the plane-marching kernels; lateral
@@ -629,7 +630,8 @@ def test_variants_bitwise_identical(wname):
          "periodic3d": lambda: _rb(36, 70, 3, walls=0),
          "thermal2d": lambda: inputs.thermal_2d(n=300, steps=6),
          "body2d": lambda: inputs.body_force_2d(n=130, steps=6),
-         "ptensor2d": lambda: inputs.ptensor_2d(n=200, steps=6, ndrops=4, rmin=10, rmax=20)}[wname]()
+         "ptensor2d": lambda: inputs.ptensor_2d(n=200, steps=6, ndrops=4, rmin=10, rmax=20),
+         "ptensor2d_256": lambda: inputs.ptensor_2d(n=256, steps=6, ndrops=4, rmin=10, rmax=20)}[wname]()
     sim = holb.Sim(w["config"])
     nv = sim.num_variants()
     sim.close()

@@ -52,7 +52,7 @@ __device__ __forceinline__ T load_at(const T* __restrict__ base, unsigned byte_o
     return *(const T*)((const char*)base + byte_off);
 }
 
-// Frame of the plane of march-axis coordinate m (FM_PLANE).
+// Frame of the plane m along the last axis (FM_PLANE).
 __device__ __forceinline__ Frame plane_frame_of(const KParams& p, int m)
 {
     Frame F;
@@ -145,7 +145,7 @@ __device__ __forceinline__ uint64_t pull_cell(const KParams& p, const typename C
             f[i] = (WALLS && ((unk >> i) & 1ull)) ? 0.0f : v;
         }
     } else {
-        // plane frames: the shift depends only on the plane, the march-axis
+        // plane frames: the shift depends only on the plane, the last-axis
         // velocity and the shell (zero within the plane)
         const int m = L::D == 3 ? z : y;
         fo = plane_frame_of(p, m);

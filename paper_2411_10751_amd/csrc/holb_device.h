@@ -12,8 +12,8 @@
 // parts instead of the variation of density and temperature across the
 // domain, so their round-off is correspondingly smaller.
 //
-// Every kernel variant (generic one-cell-per-thread, plane-marching, batched)
-// calls the same inline functions below, and the library is compiled with
+// Every kernel variant (the block orders of the generic kernels, the batched
+// form) calls the same inline functions below, and the library is compiled with
 // -ffp-contract=off and explicit fmaf(), so the per-cell arithmetic -- and
 // therefore the result -- is bitwise identical across tilings.
 #pragma once

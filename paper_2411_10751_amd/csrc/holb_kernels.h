@@ -80,7 +80,7 @@ k_plane_frames(const KParams p, const float* __restrict__ rho, const float* __re
 }
 
 // Shift table of the per-plane frames: R_s(frame(m - c_m)) - R_s(frame(m)) for
-// every plane m, march-axis velocity c_m in [-3, 3] and shell s (zero where
+// every plane m, last-axis velocity component c_m in [-3, 3] and shell s (zero where
 // plane m - c_m lies beyond a wall: those populations are rebuilt, not read).
 template <class L>
 __global__ void k_plane_shift(const KParams p, const float* __restrict__ frames, float* __restrict__ shifts)

@@ -72,7 +72,7 @@ struct KParams {
     unsigned* err;       // device error word
     // FM_PLANE: rho and theta - 1 of each plane along the last axis (2 floats
     // per plane), and the shifts R_s(frame(m - c_m)) - R_s(frame(m)) at
-    // [(m * 7 + c_m + 3) * NS + s] for plane m, march-axis velocity c_m, shell s
+    // [(m * 7 + c_m + 3) * NS + s] for plane m, last-axis velocity component c_m, shell s
     const float* plane_frame;
     const float* plane_shift;
 };

@@ -620,9 +620,9 @@ def test_batched_graph_replay_matches_eager():
 @pytest.mark.parametrize("wname", ["rb3d", "rb3d_tall", "periodic3d", "thermal2d", "body2d", "ptensor2d",
                                    "ptensor2d_256"])
 def test_variants_bitwise_identical(wname):
-    """Every kernel variant of a configuration gives bitwise identical fields
-    (tall boxes span several chunks of the plane-marching kernels; lateral
-    sizes that are no multiple of the tiles leave ragged tiles)."""
+    """Every kernel variant (block order) of a configuration gives bitwise
+    identical fields, on boxes whose sizes leave partial blocks and on a
+    256-wide grid whose blocks each lie in one row."""
     import torch
     from paper_2411_10751_amd import holb
     w = {"rb3d": lambda: _rb(40, 24, 6),

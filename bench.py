@@ -307,10 +307,10 @@ def main():
             "walls": cfg["walls"],
             "storage": args.storage,
             "variant": variant,
-            # frames as the library resolves them (auto: per plane for FP32 with
-            # walls, per cell otherwise)
+            # frames as the library resolves them (auto: per plane for FP32 and
+            # FP16 with walls, per cell otherwise)
             "frames": {1: "cell", 2: "plane", 3: "cellu"}.get(
-                frames, "plane" if storage == 0 and cfg.get("walls") else "cell"),
+                frames, "plane" if storage != 2 and cfg.get("walls") else "cell"),
             "mass": totals[0],
         },
         "roofline": {

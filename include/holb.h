@@ -74,13 +74,13 @@ typedef int32_t holb_status;
  * PLANE keeps one fixed frame per plane along the last axis (the plane means
  * of the initial fields): nothing per cell, and suited to states whose
  * density and temperature vary mostly along that axis -- it keeps less of the
- * FP32 precision where the state drifts far from those means.  PLANE is FP32
- * only.  CELL_U (16-bit storage only) adds the cell's momentum to its frame,
+ * precision where the state drifts far from those means.  CELL_U (16-bit
+ * storage only) adds the cell's momentum to its frame,
  * so that the stored deviations lose their first-order velocity part as well:
  * about 3x smaller BF16 errors in flows with O(0.05) velocities, for a second
  * round of Q - 1 loads per pull (at 256^3 about 1.5x the step time of CELL).
- * AUTO picks PLANE for FP32 storage with walls (which impose the mean profile
- * along the wall-normal axis) and CELL otherwise. */
+ * AUTO picks PLANE for FP32 and FP16 storage with walls (which impose the
+ * mean profile along the wall-normal axis) and CELL otherwise. */
 #define HOLB_FRAMES_AUTO 0
 #define HOLB_FRAMES_CELL 1
 #define HOLB_FRAMES_PLANE 2

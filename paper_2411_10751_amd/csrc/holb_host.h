@@ -65,8 +65,6 @@ inline holb_status validate(const holb_config* c)
     if (c->walls != 0 && c->walls != 1) return fail(HOLB_EINVAL, "walls must be 0 or 1");
     if (c->frames < HOLB_FRAMES_AUTO || c->frames > HOLB_FRAMES_CELL_U)
         return fail(HOLB_EINVAL, "frames must be one of HOLB_FRAMES_*");
-    if (c->frames == HOLB_FRAMES_PLANE && c->storage != HOLB_STORE_F32)
-        return fail(HOLB_EUNSUPPORTED, "per-plane frames are for FP32 storage only");
     if (c->frames == HOLB_FRAMES_CELL_U && c->storage == HOLB_STORE_F32)
         return fail(HOLB_EUNSUPPORTED, "per-cell frames with momentum are for 16-bit storage only");
     for (int a = 0; a < 3; ++a)
@@ -108,15 +106,16 @@ inline holb_status validate(const holb_config* c)
 }
 
 // Frame mode of a configuration.  HOLB_FRAMES_AUTO takes per-plane frames
-// for FP32 storage in a walled domain (whose walls impose the mean profile
-// along the wall-normal axis) and per-cell frames otherwise; frames with
+// for FP32 and FP16 storage in a walled domain (whose walls impose the mean
+// profile along the wall-normal axis) and per-cell frames otherwise (BF16,
+// with 8 significand bits, needs the closer per-cell frames); frames with
 // momentum are taken only when asked for.
 inline int frames_of(const holb_config* c)
 {
     if (c->frames == HOLB_FRAMES_CELL) return FM_CELL;
     if (c->frames == HOLB_FRAMES_PLANE) return FM_PLANE;
     if (c->frames == HOLB_FRAMES_CELL_U) return FM_CELLU;
-    return (c->storage == HOLB_STORE_F32 && c->walls) ? FM_PLANE : FM_CELL;
+    return (c->walls && c->storage != HOLB_STORE_BF16DEV) ? FM_PLANE : FM_CELL;
 }
 
 inline KParams params_of(const holb_config* c)

@@ -419,6 +419,10 @@ inline hipError_t dispatch_set(const LaunchCtx& c, int op, const float* a, const
         if (c.frames == FM_PLANE) return dispatch_family<L, ST_F32, FM_PLANE>(c, op, a, b, d, o1, o2, o3, dout);
         return dispatch_family<L, ST_F32, FM_CELL>(c, op, a, b, d, o1, o2, o3, dout);
     } else {
+        if (c.frames == FM_PLANE) {
+            if (c.storage == ST_F16) return dispatch_family<L, ST_F16, FM_PLANE>(c, op, a, b, d, o1, o2, o3, dout);
+            return dispatch_family<L, ST_BF16, FM_PLANE>(c, op, a, b, d, o1, o2, o3, dout);
+        }
         if (c.frames == FM_CELLU) {
             if (c.storage == ST_F16) return dispatch_family<L, ST_F16, FM_CELLU>(c, op, a, b, d, o1, o2, o3, dout);
             return dispatch_family<L, ST_BF16, FM_CELLU>(c, op, a, b, d, o1, o2, o3, dout);

@@ -72,7 +72,6 @@ def _cfg(**kw):
     (dict(g=(float("inf"), 0, 0)), holb.EINVAL),
     (dict(lattice=1, nx=1024, ny=1024, nz=1024), holb.ESIZE),
     (dict(frames=4), holb.EINVAL),
-    (dict(storage=1, rho0=1.0, frames=2), holb.EUNSUPPORTED),
     (dict(storage=0, frames=3), holb.EUNSUPPORTED),
 ])
 def test_config_errors(bad, code):
@@ -128,13 +127,13 @@ def test_create_is_host_only_and_checks_workspace():
 
 
 @pytest.mark.parametrize("walls,storage,frames,per_cell", [
-    (1, 0, 0, 0), (1, 0, 1, 4), (0, 0, 0, 4), (0, 0, 2, 0), (1, 1, 0, 4), (0, 2, 0, 4), (1, 2, 0, 4),
-    (0, 1, 3, 8), (0, 2, 1, 4), (0, 2, 3, 8)])
+    (1, 0, 0, 0), (1, 0, 1, 4), (0, 0, 0, 4), (0, 0, 2, 0), (1, 1, 0, 0), (0, 1, 0, 4), (0, 2, 0, 4), (1, 2, 0, 4),
+    (0, 1, 3, 8), (0, 2, 1, 4), (0, 2, 3, 8), (1, 1, 2, 0), (1, 2, 2, 0)])
 def test_state_layout_by_frame_mode(walls, storage, frames, per_cell):
     """The raw state holds the Q planes, then per_cell bytes of frame words per
     cell (4 for per-cell frames, 8 with momentum, in two planes) or the per-plane table of
-    2 + 7 NS floats per plane; AUTO picks per-plane frames for FP32 with walls
-    and per-cell frames otherwise."""
+    2 + 7 NS floats per plane; AUTO picks per-plane frames for FP32 and FP16
+    with walls and per-cell frames otherwise."""
     nx, ny, nz = 24, 20, 15  # N = 7200: the frame planes need padding
     cfg = holb.make_config(dict(lattice=1, nx=nx, ny=ny, nz=nz, tau_hat=0.8, sources=3, prandtl=0.7,
                                 g=(0, 0, -1e-5), walls=walls, storage=storage, frames=frames, rho0=1.0,

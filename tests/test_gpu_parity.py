@@ -167,13 +167,14 @@ def _rb_mid_oracle():
     return _RB_MID["w"], _RB_MID["o"]
 
 
-@pytest.mark.parametrize("storage,frames", [(0, 0), (1, 0), pytest.param(2, 0, marks=pytest.mark.xfail(
+@pytest.mark.parametrize("storage,frames", [(0, 0), (1, 0), (1, 1), pytest.param(2, 0, marks=pytest.mark.xfail(
     reason="BF16 with per-cell frames reaches 2.8e-3 in u on this box, against the 2e-3 bound", strict=False)),
     (2, 3)])
 def test_rb3d_walls_mid(storage, frames):
-    """FP32, FP16 and BF16 with their default frames, and BF16 with momentum
-    frames, which keep it within the bound (u 8e-4 in the oracle-side
-    emulation of the storage rounding)."""
+    """FP32, FP16 and BF16 with their default frames (per plane, per plane,
+    per cell), FP16 with per-cell frames, and BF16 with momentum frames, which
+    keep it within the bound (u 8e-4 in the oracle-side emulation of the
+    storage rounding)."""
     w, o = _rb_mid_oracle()
     log("case %s storage %d frames %d" % (w["name"], storage, frames))
     cfg = dict(w["config"], frames=frames)
@@ -181,13 +182,15 @@ def test_rb3d_walls_mid(storage, frames):
     assert_parity(g, o, 1, TOL[storage], w["name"] + " st%d fr%d" % (storage, frames))
 
 
-@pytest.mark.parametrize("storage", [1])
-def test_rb3d_walls_16bit(storage):
+@pytest.mark.parametrize("frames", [0, 1])
+def test_rb3d_walls_16bit(frames):
     """FP16 on the small box, whose gradients are 14 times those of the 256^3
-    workload (BF16 keeps 8 bits and is checked on the larger box above)."""
+    workload, with its default (per-plane) and with per-cell frames (BF16
+    keeps 8 bits and is checked on the larger box above)."""
     w = _rb_small()
-    g, o = _both(w, storage=storage)
-    assert_parity(g, o, 1, TOL[storage], w["name"] + " st%d" % storage)
+    w["config"] = dict(w["config"], frames=frames)
+    g, o = _both(w, storage=1)
+    assert_parity(g, o, 1, TOL[1], w["name"] + " st1 fr%d" % frames)
 
 
 def test_periodic_3d_thermal_body():
@@ -335,6 +338,7 @@ def test_full_thermal_1024_full_horizon(storage, frames):
 
 @pytest.mark.parametrize("storage", [0, 1, 2])
 def test_full_rb3d_256_column_horizon(storage):
+    # default frames: per plane for FP32 and FP16, per cell for BF16
     """The 256^3 Rayleigh-Benard box over the benchmark's 200 steps, started
     without the noise so that the exact solution depends on z only: the FP64
     oracle runs one 1 x 1 x 256 column (periodic in x and y, the same walls

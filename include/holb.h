@@ -186,6 +186,12 @@ holb_status holb_error_flags(holb_sim* s, uint32_t* flags);
  *   PLANE:  no per-cell words; after the planes (256-byte aligned) a float
  *           table of (rho_F, theta_F - 1) per plane along the last axis,
  *           then R_s(plane m - c_m) - R_s(plane m) at [(m 7 + c_m + 3) NS + s].
+ * With walls, the wall targets follow (again 256-byte aligned): for the
+ * three layers next to each wall (layer k = 0, 1, 2 from the low wall, then
+ * n-3, n-2, n-1), the last step's rho, u[D] and theta, each a plane of the
+ * layer's cells (float).  Restoring them makes a resumed walled run
+ * continue bitwise as the uninterrupted one.  holb_set_state needs no
+ * holb_init before it and clears the device error flags.
  * Slot i of cell y holds the post-collision population f*_i(y) of the last
  * step in the frame F of y: h = f*_i / w_i - rho_F (1 + t_i(u = 0, theta_F))
  * of Eq. (2.2) (CELL_U: minus c_i . P as well) in FP32 storage, h - d_i

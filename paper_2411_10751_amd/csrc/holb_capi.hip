@@ -258,21 +258,27 @@ holb_status holb_error_flags(holb_sim* s, uint32_t* flags)
     return HOLB_OK;
 }
 
+// State blob: the current population buffer, then the per-plane table (if
+// any), then the wall targets of the next step (walled domains: the last
+// step's rho, u, theta on the three layers next to each wall).
 holb_status holb_state_bytes(holb_sim* s, size_t* bytes)
 {
     if (!s || !bytes) return fail(HOLB_EINVAL, "NULL argument");
-    *bytes = s->lay.pop_bytes + s->lay.tab_bytes;
+    *bytes = s->lay.pop_bytes + s->lay.tab_bytes + s->lay.tgt_bytes;
     return HOLB_OK;
 }
 
 holb_status holb_get_state(holb_sim* s, void* dst, size_t bytes)
 {
     if (!s || !dst) return fail(HOLB_EINVAL, "NULL argument");
-    const size_t pb = s->lay.pop_bytes, tb = s->lay.tab_bytes;
-    if (bytes != pb + tb) return fail(HOLB_ESIZE, "state is %zu bytes, got %zu", pb + tb, bytes);
+    const size_t pb = s->lay.pop_bytes, tb = s->lay.tab_bytes, gb = s->lay.tgt_bytes;
+    if (bytes != pb + tb + gb) return fail(HOLB_ESIZE, "state is %zu bytes, got %zu", pb + tb + gb, bytes);
     hipError_t e = hipMemcpyAsync(dst, s->ws + s->lay.pop_off[s->cur], pb, hipMemcpyDeviceToDevice, s->stream);
     if (e == hipSuccess && tb)
         e = hipMemcpyAsync((char*)dst + pb, s->ws + s->lay.tab_off, tb, hipMemcpyDeviceToDevice, s->stream);
+    if (e == hipSuccess && gb)
+        e = hipMemcpyAsync((char*)dst + pb + tb, s->ws + s->lay.tgt_off[s->cur], gb, hipMemcpyDeviceToDevice,
+                           s->stream);
     if (e != hipSuccess) return hip_fail(e, "copying the state out");
     return HOLB_OK;
 }
@@ -280,12 +286,17 @@ holb_status holb_get_state(holb_sim* s, void* dst, size_t bytes)
 holb_status holb_set_state(holb_sim* s, const void* src, size_t bytes)
 {
     if (!s || !src) return fail(HOLB_EINVAL, "NULL argument");
-    const size_t pb = s->lay.pop_bytes, tb = s->lay.tab_bytes;
-    if (bytes != pb + tb) return fail(HOLB_ESIZE, "state is %zu bytes, got %zu", pb + tb, bytes);
-    if (s->cfg.walls && !s->initialized) return fail(HOLB_ESTATE, "walled domains need holb_init before holb_set_state");
-    hipError_t e = hipMemcpyAsync(s->ws + s->lay.pop_off[s->cur], src, pb, hipMemcpyDeviceToDevice, s->stream);
+    const size_t pb = s->lay.pop_bytes, tb = s->lay.tab_bytes, gb = s->lay.tgt_bytes;
+    if (bytes != pb + tb + gb) return fail(HOLB_ESIZE, "state is %zu bytes, got %zu", pb + tb + gb, bytes);
+    // a fresh simulation may take a state without holb_init: clear its flags
+    hipError_t e = hipMemsetAsync(s->ws + s->lay.err_off, 0, sizeof(unsigned), s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->ws + s->lay.pop_off[s->cur], src, pb, hipMemcpyDeviceToDevice, s->stream);
     if (e == hipSuccess && tb)
         e = hipMemcpyAsync(s->ws + s->lay.tab_off, (const char*)src + pb, tb, hipMemcpyDeviceToDevice, s->stream);
+    if (e == hipSuccess && gb)
+        e = hipMemcpyAsync(s->ws + s->lay.tgt_off[s->cur], (const char*)src + pb + tb, gb, hipMemcpyDeviceToDevice,
+                           s->stream);
     if (e != hipSuccess) return hip_fail(e, "copying the state in");
     s->initialized = true;
     return HOLB_OK;

@@ -174,14 +174,14 @@ __device__ __forceinline__ uint64_t pull_cell(const KParams& p, const typename C
         } else {
 #pragma unroll
             for (int i = 1; i < L::Q; ++i) {
-                const int sx = wrapc(x - L::cx[i], p.nx);
+                const int sx = wrap_seq(x - L::cx[i], p.nx);
                 int sy = y - L::cy[i], sz = z - L::cz[i];
                 if (L::D == 2) {
                     sz = 0;
-                    sy = (WALLS && p.walls) ? min(max(sy, 0), p.ny - 1) : wrapc(sy, p.ny);
+                    sy = (WALLS && p.walls) ? min(max(sy, 0), p.ny - 1) : wrap_seq(sy, p.ny);
                 } else {
-                    sy = wrapc(sy, p.ny);
-                    sz = (WALLS && p.walls) ? min(max(sz, 0), p.nz - 1) : wrapc(sz, p.nz);
+                    sy = wrap_seq(sy, p.ny);
+                    sz = (WALLS && p.walls) ? min(max(sz, 0), p.nz - 1) : wrap_seq(sz, p.nz);
                 }
                 // an unknown population reads a clamped slot; its value is discarded
                 mw[i] = load_at(mp, (unsigned)((sz * p.ny + sy) * p.nx + sx) * 4u);
@@ -294,16 +294,30 @@ __device__ __forceinline__ void sc_force(const KParams& p, const double* __restr
                                          double& psi_x, double (&F)[3])
 {
     double acc[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int i = 1; i < L::Q; ++i) {
-        const int sx = wrapc(x + L::cx[i], p.nx), sy = wrapc(y + L::cy[i], p.ny);
-        const int sz = L::D == 3 ? wrapc(z + L::cz[i], p.nz) : 0;
-        const double ps = psi[(sz * p.ny + sy) * p.nx + sx] * L::shell_w[L::shell[i]];
+    const int cell = (z * p.ny + y) * p.nx + x;
+    // Sums in velocity order.  A wavefront whose lanes all lie at least 3
+    // cells from every edge reads neighbour i at a wave-uniform base
+    // psi + shift_i and one shared lane offset; the others wrap per coordinate.
+    auto add = [&](int i, double v) {
+        const double ps = v * L::shell_w[L::shell[i]];
         if (L::cx[i]) acc[0] = fma((double)L::cx[i], ps, acc[0]);
         if (L::cy[i]) acc[1] = fma((double)L::cy[i], ps, acc[1]);
         if (L::cz[i]) acc[2] = fma((double)L::cz[i], ps, acc[2]);
+    };
+    const bool inner = x >= 3 && x < p.nx - 3 && y >= 3 && y < p.ny - 3 && (L::D == 2 || (z >= 3 && z < p.nz - 3));
+    if (__all(inner)) {
+        const unsigned cb = (unsigned)cell * (unsigned)sizeof(double);
+#pragma unroll
+        for (int i = 1; i < L::Q; ++i) add(i, load_at(psi + (L::cz[i] * p.ny + L::cy[i]) * p.nx + L::cx[i], cb));
+    } else {
+#pragma unroll
+        for (int i = 1; i < L::Q; ++i) {
+            const int sx = wrapc(x + L::cx[i], p.nx), sy = wrapc(y + L::cy[i], p.ny);
+            const int sz = L::D == 3 ? wrapc(z + L::cz[i], p.nz) : 0;
+            add(i, psi[(sz * p.ny + sy) * p.nx + sx]);
+        }
     }
-    psi_x = psi[(z * p.ny + y) * p.nx + x];
+    psi_x = psi[cell];
 #pragma unroll
     for (int a = 0; a < 3; ++a) F[a] = -p.G * psi_x * acc[a];
 }
@@ -321,9 +335,23 @@ template <class L>
 __device__ __forceinline__ void grad_theta(const KParams& p, const float* __restrict__ th, int x, int y, int z,
                                            float (&g)[3])
 {
+    g[2] = 0.0f;
+    // A wavefront with every lane off the edges of the other axes takes their
+    // central differences at wave-uniform bases and one shared lane offset;
+    // x wraps by a select.
+    const bool inner_yz = y >= 1 && y < p.ny - 1 && (L::D == 2 || (z >= 1 && z < p.nz - 1));
+    if (__all(inner_yz)) {
+        const int cell = (z * p.ny + y) * p.nx + x;
+        const unsigned cb = (unsigned)cell * 4u;
+        const int row = cell - x;
+        const int xp = x + 1 < p.nx ? x + 1 : 0, xm = x > 0 ? x - 1 : p.nx - 1;
+        g[0] = 0.5f * (th[row + xp] - th[row + xm]);
+        g[1] = 0.5f * (load_at(th + p.nx, cb) - load_at(th - p.nx, cb));
+        if (L::D == 3) g[2] = 0.5f * (load_at(th + p.nx * p.ny, cb) - load_at(th - p.nx * p.ny, cb));
+        return;
+    }
     auto at = [&](int xx, int yy, int zz) { return th[(zz * p.ny + yy) * p.nx + xx]; };
     g[0] = 0.5f * (at(wrapc(x + 1, p.nx), y, z) - at(wrapc(x - 1, p.nx), y, z));
-    g[2] = 0.0f;
     if (L::D == 2) {
         if (p.walls) {
             if (y == 0) g[1] = at(x, 1, z) - at(x, 0, z);

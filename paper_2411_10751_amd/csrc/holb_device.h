@@ -79,7 +79,27 @@ struct Codec<ST_BF16> {
 
 // -------------------------------------------------------- small helpers
 
+// Periodic wrap of a coordinate.  The stencils reach at most 3 cells past
+// an edge, so one correction each way suffices on axes of 3 cells or more;
+// the loop runs only on shorter axes (a branch the waves of larger domains
+// skip: written as a bare loop, the wrap costs about 20 VALU per call).
 __device__ __forceinline__ int wrapc(int v, int n)
+{
+    v = v < 0 ? v + n : v;
+    v = v >= n ? v - n : v;
+    if ((unsigned)v >= (unsigned)n) {
+        while (v < 0) v += n;
+        while (v >= n) v -= n;
+    }
+    return v;
+}
+
+// The same wrap as bare loops, for sequences of dependent loads on edge
+// waves only: the loops keep each address next to its load, where the
+// branch-free form lets the compiler compute every address of the sequence
+// ahead and hold them all in registers (costing a wave of occupancy in the
+// momentum phase of the per-cell momentum frames).
+__device__ __forceinline__ int wrap_seq(int v, int n)
 {
     while (v < 0) v += n;
     while (v >= n) v -= n;

@@ -204,3 +204,36 @@ int main() {
     subprocess.run(["g++", "-O2", "-D__host__=", "-D__device__=", "-I" + inc, str(src), "-o", str(exe)], check=True)
     r = subprocess.run([str(exe)], capture_output=True, text=True)
     assert r.returncode == 0 and r.stdout.strip() == "0", r.stdout
+
+
+def test_periodic_wrap_exact(tmp_path):
+    """The periodic wrap of the stencils (one select each way, a loop only on
+    axes shorter than the reach) equals the mathematical modulo for every
+    offset the stencils use (up to 3 cells past either edge) on every axis
+    length from 1 to 300, as does the loop form used on edge waves."""
+    text = open(os.path.join(ROOT, "paper_2411_10751_amd", "csrc", "holb_device.h")).read()
+    funcs = []
+    for name in ("wrapc", "wrap_seq"):
+        start = text.index("__device__ __forceinline__ int %s(int v, int n)" % name)
+        end = text.index("\n}\n", start) + 3
+        funcs.append(text[start:end])
+    src = tmp_path / "wrap.cpp"
+    src.write_text("#include <cstdio>\n#define __device__\n#define __forceinline__ inline\n" + "".join(funcs) + r'''
+int main() {
+    unsigned long long bad = 0, n_cases = 0;
+    for (int n = 1; n <= 300; ++n)
+        for (int x = 0; x < n; ++x)
+            for (int c = -3; c <= 3; ++c) {
+                const int v = x + c, m = ((v % n) + n) % n;
+                bad += wrapc(v, n) != m;
+                bad += wrap_seq(v, n) != m;
+                ++n_cases;
+            }
+    printf("%llu %llu\n", bad, n_cases);
+    return bad != 0;
+}
+''')
+    exe = tmp_path / "wrap"
+    subprocess.run(["g++", "-O2", str(src), "-o", str(exe)], check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0 and r.stdout.split()[0] == "0", r.stdout

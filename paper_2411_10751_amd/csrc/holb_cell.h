@@ -52,6 +52,35 @@ __device__ __forceinline__ T load_at(const T* __restrict__ base, unsigned byte_o
     return *(const T*)((const char*)base + byte_off);
 }
 
+// The same with the base made opaque by an empty asm (which also pins it to
+// scalar registers), for the population loads of the interior pull, whose
+// bases differ per population: otherwise the compiler folds each base into
+// a per-lane 64-bit address, one or two vector instructions per load
+// (quarter-rate multiply-adds among them).  The base must be the same on all
+// lanes of a wavefront.  Only for loads that are all issued before any is
+// consumed: the asm also keeps the scheduler from moving a load across it.
+template <class T>
+__device__ __forceinline__ T load_uniform_at(const T* __restrict__ base, unsigned byte_off)
+{
+    using GT = const __attribute__((address_space(1))) T;
+    using GC = const __attribute__((address_space(1))) char;
+    GT* g = (GT*)base;
+    asm("" : "+s"(g));
+    return *(GT*)((GC*)g + byte_off);
+}
+
+// Non-temporal store at a 32-bit byte offset from a wave-uniform base, made
+// opaque in the same way (the stores of a node go to Q different planes).
+template <class T>
+__device__ __forceinline__ void store_nt_at(T* __restrict__ base, unsigned byte_off, T v)
+{
+    using GT = __attribute__((address_space(1))) T;
+    using GC = __attribute__((address_space(1))) char;
+    GT* g = (GT*)base;
+    asm("" : "+s"(g));
+    __builtin_nontemporal_store(v, (GT*)((GC*)g + byte_off));
+}
+
 // Frame of the plane m along the last axis (FM_PLANE).
 __device__ __forceinline__ Frame plane_frame_of(const KParams& p, int m)
 {
@@ -91,7 +120,7 @@ __device__ __forceinline__ uint64_t pull_cell(const KParams& p, const typename C
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) {
             const int shift = (L::cz[i] * p.ny + L::cy[i]) * p.nx + L::cx[i];
-            raw[i] = load_at(fin + ((long long)i * p.pitch - shift), cb);
+            raw[i] = load_uniform_at(fin + ((long long)i * p.pitch - shift), cb);
             if (CF) fw[i] = load_at(fp - shift, cf);
             if (CU && MOM1) mw[i] = load_at(mp - shift, cf);
         }
@@ -208,6 +237,9 @@ __device__ __forceinline__ void store_cell(const KParams& p, typename Codec<ST>:
                                            float (&f)[L::Q], const Frame& fo, float rho, float thb,
                                            const float (&u)[3])
 {
+    // wave-uniform plane bases and one shared lane offset: the address of
+    // each store costs no vector instructions
+    const unsigned cb = (unsigned)cell * (unsigned)sizeof(typename Codec<ST>::T);
     if constexpr (FM == FM_CELLU) {
         const uint32_t packed = pack_frame(rho, thb);
         float P[3];
@@ -222,15 +254,14 @@ __device__ __forceinline__ void store_cell(const KParams& p, typename Codec<ST>:
         float sh[L::NS];  // R(fo) - R(fn)
 #pragma unroll
         for (int s = 0; s < L::NS; ++s) sh[s] = -frame_shift<L>(ref, s, fn);
-        __builtin_nontemporal_store(Codec<ST>::enc(f[0] + sh[0], p.dref[0]), fout + cell);
+        store_nt_at(fout, cb, Codec<ST>::enc(f[0] + sh[0], p.dref[0]));
         // +/-c pairs share c . P with opposite signs
 #pragma unroll
         for (int i = 1; i < L::Q; i += 2) {
             const float cp = cdot_mom<L>(i, mom);
             const float s = sh[L::shell[i]];
-            __builtin_nontemporal_store(Codec<ST>::enc(f[i] + s - cp, p.dref[i]), fout + (long long)i * p.pitch + cell);
-            __builtin_nontemporal_store(Codec<ST>::enc(f[i + 1] + s + cp, p.dref[i + 1]),
-                                        fout + (long long)(i + 1) * p.pitch + cell);
+            store_nt_at(fout + (long long)i * p.pitch, cb, Codec<ST>::enc(f[i] + s - cp, p.dref[i]));
+            store_nt_at(fout + (long long)(i + 1) * p.pitch, cb, Codec<ST>::enc(f[i + 1] + s + cp, p.dref[i + 1]));
         }
     } else if constexpr (FM == FM_CELL) {
         const uint32_t packed = pack_frame(rho, thb);
@@ -242,12 +273,10 @@ __device__ __forceinline__ void store_cell(const KParams& p, typename Codec<ST>:
         for (int s = 0; s < L::NS; ++s) sh[s] = -frame_shift<L>(ref, s, fn);
 #pragma unroll
         for (int i = 0; i < L::Q; ++i)
-            __builtin_nontemporal_store(Codec<ST>::enc(f[i] + sh[L::shell[i]], p.dref[i]),
-                                        fout + (long long)i * p.pitch + cell);
+            store_nt_at(fout + (long long)i * p.pitch, cb, Codec<ST>::enc(f[i] + sh[L::shell[i]], p.dref[i]));
     } else {
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i)
-            __builtin_nontemporal_store(Codec<ST>::enc(f[i], p.dref[i]), fout + (long long)i * p.pitch + cell);
+        for (int i = 0; i < L::Q; ++i) store_nt_at(fout + (long long)i * p.pitch, cb, Codec<ST>::enc(f[i], p.dref[i]));
     }
 }
 

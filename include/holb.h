@@ -244,6 +244,16 @@ holb_status holb_batch_init(holb_batch* b, const float* const* rho, const float*
 holb_status holb_batch_step(holb_batch* b, int64_t n);
 holb_status holb_batch_fields(holb_batch* b, int32_t run, float* rho, float* u, float* theta);
 holb_status holb_batch_reduce(holb_batch* b, int32_t run, double out[5]);
+/* Launch shape of the batched kernels.  Variant v in [0, 12) splits every
+ * run into work items of 256 << (v / 3) consecutive cells (256 to 2048; a
+ * block takes an item 256 cells at a time) and runs a persistent grid of 4, 8
+ * or 2 blocks per compute unit (v % 3) over the work list; 0 is the default.
+ * Results are bitwise identical across variants.  holb_batch_set_variant
+ * uploads the work list of the new item size on the handle's stream and
+ * synchronises it (HOLB_EUNSUPPORTED outside [0, 12)).  holb_batch_tune times
+ * three steps of every variant (they write the idle buffer, so the state is
+ * unchanged), keeps the fastest and returns it in variant_out (may be NULL);
+ * it synchronises and needs holb_batch_init first (else HOLB_ESTATE). */
 holb_status holb_batch_tune(holb_batch* b, int32_t* variant_out);
 holb_status holb_batch_set_variant(holb_batch* b, int32_t variant);
 /* Instrumentation, as holb_timing_start / holb_timing_stop: while a timing is

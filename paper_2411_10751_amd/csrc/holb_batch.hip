@@ -59,36 +59,46 @@ __device__ __forceinline__ KParams run_params(const RunDesc& r, unsigned* err, c
 
 template <int FAM>
 __global__ void __launch_bounds__(BATCH_ITEM)
-k_batch_aux(const RunDesc* __restrict__ runs, const int2* __restrict__ items, int nitems,
+k_batch_aux(const RunDesc* __restrict__ runs, const int2* __restrict__ items, int nitems, int tile,
             const float* __restrict__ fin, float* __restrict__ aux, const float* __restrict__ tgi, unsigned* err,
             const float* __restrict__ tab)
 {
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const int2 t = items[it];
-        const RunDesc r = runs[t.x];
-        const int cell = t.y + threadIdx.x;
-        if (cell < r.N) {
+        for (int c0 = t.y;; c0 += BATCH_ITEM) {
+            asm volatile("" ::: "memory");
+            const RunDesc r = runs[t.x];
+            const int end = min(t.y + tile, r.N);
+            if (c0 >= end) break;
             const KParams p = run_params(r, err, tab);
-            aux_cell<D2Q37, ST_F32, FAM, false, FM_PLANE>(p, fin + r.off, tgi, aux + r.cell0, nullptr, cell);
+            const int cell = c0 + threadIdx.x;
+            if (cell < end)
+                aux_cell<D2Q37, ST_F32, FAM, false, FM_PLANE>(p, fin + r.off, tgi, aux + r.cell0, nullptr, cell);
         }
     }
 }
 
 template <int FAM>
 __global__ void __launch_bounds__(BATCH_ITEM)
-k_batch_step(const RunDesc* __restrict__ runs, const int2* __restrict__ items, int nitems,
+k_batch_step(const RunDesc* __restrict__ runs, const int2* __restrict__ items, int nitems, int tile,
              const float* __restrict__ fin, float* __restrict__ fout, const float* __restrict__ aux,
              const double* __restrict__ auxd, const float* __restrict__ tgi, float* __restrict__ tgo, unsigned* err,
              const float* __restrict__ tab)
 {
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const int2 t = items[it];
-        const RunDesc r = runs[t.x];
-        const int cell = t.y + threadIdx.x;
-        if (cell < r.N) {
+        for (int c0 = t.y;; c0 += BATCH_ITEM) {
+            // the run's parameters are re-read per chunk: held across the
+            // chunks of an item they would cost a wave of occupancy
+            asm volatile("" ::: "memory");
+            const RunDesc r = runs[t.x];
+            const int end = min(t.y + tile, r.N);
+            if (c0 >= end) break;
             const KParams p = run_params(r, err, tab);
-            step_cell<D2Q37, ST_F32, FAM, false, FM_PLANE>(p, fin + r.off, fout + r.off, aux + r.cell0, auxd, tgi, tgo,
-                                                           cell);
+            const int cell = c0 + threadIdx.x;
+            if (cell < end)
+                step_cell<D2Q37, ST_F32, FAM, false, FM_PLANE>(p, fin + r.off, fout + r.off, aux + r.cell0, auxd, tgi,
+                                                               tgo, cell);
         }
     }
 }
@@ -135,11 +145,27 @@ struct holb_batch {
     float* tab() const { return (float*)(ws + tab_off); }
     unsigned* err() const { return (unsigned*)(ws + err_off); }
 
-    // persistent grid: a few blocks per compute unit, walking the work list
-    int grid() const
+    // Launch shape of a variant v in [0, BATCH_VARIANTS): work items of
+    // 256 << (v / 3) consecutive cells of one run (a block takes them 256 at a
+    // time), and a persistent grid of 4, 8 or 2 blocks per compute unit
+    // (v % 3) walking the work list.  Every cell is computed by the same code
+    // whichever block takes it, so the variants agree bitwise.
+    static int tile_of(int v) { return BATCH_ITEM << (v / 3); }
+    static int per_cu_of(int v)
     {
-        const int per_cu = variant == 2 ? 8 : 4;
-        return std::max(1, std::min((int)items.size(), 256 * per_cu));
+        static const int k[3] = {4, 8, 2};
+        return k[v % 3];
+    }
+    int tile = BATCH_ITEM;  // cells per work item of the uploaded list
+    int grid() const { return std::max(1, std::min((int)items.size(), 256 * per_cu_of(variant))); }
+
+    // Work list for items of `t` cells: (run, first cell) of each item.
+    void build_items(int t)
+    {
+        items.clear();
+        for (int r = 0; r < n; ++r)
+            for (int c0 = 0; c0 < runs[r].N; c0 += t) items.push_back(make_int2(r, c0));
+        tile = t;
     }
 
     // One step: the temperature pass (thermal family), then the collision
@@ -151,7 +177,7 @@ struct holb_batch {
         float* fout = pop(1 - from);
         if (fam == FAM_THERMAL) {
             hipLaunchKernelGGL(k_batch_aux<FAM_THERMAL>, dim3(grid()), dim3(BATCH_ITEM), 0, s, d_runs(), d_items(),
-                               nit, fin, aux(), (const float*)nullptr, err(), (const float*)tab());
+                               nit, tile, fin, aux(), (const float*)nullptr, err(), (const float*)tab());
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
@@ -161,11 +187,11 @@ struct holb_batch {
         }
         if (fam == FAM_THERMAL)
             hipLaunchKernelGGL(k_batch_step<FAM_THERMAL>, dim3(grid()), dim3(BATCH_ITEM), 0, s, d_runs(),
-                               d_items(), nit, fin, fout, (const float*)aux(), (const double*)nullptr,
+                               d_items(), nit, tile, fin, fout, (const float*)aux(), (const double*)nullptr,
                                (const float*)nullptr, (float*)nullptr, err(), (const float*)tab());
         else
             hipLaunchKernelGGL(k_batch_step<FAM_LOCAL>, dim3(grid()), dim3(BATCH_ITEM), 0, s, d_runs(), d_items(),
-                               nit, fin, fout, (const float*)aux(), (const double*)nullptr, (const float*)nullptr,
+                               nit, tile, fin, fout, (const float*)aux(), (const double*)nullptr, (const float*)nullptr,
                                (float*)nullptr, err(), (const float*)tab());
         hipError_t e = hipGetLastError();
         if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
@@ -252,9 +278,10 @@ void plan(holb_batch* b, const holb_config* cfgs, int n)
         d.tab = (long long)tabf;
         tabf += (size_t)(2 + 7 * D2Q37::NS) * c.ny;
         cells += align_up((size_t)d.N, 64);
-        for (int c0 = 0; c0 < d.N; c0 += BATCH_ITEM) b->items.push_back(make_int2(r, c0));
         maxblk = std::max(maxblk, (d.N + 255) / 256);
     }
+    // the list of the smallest items is the longest: the workspace holds it
+    b->build_items(BATCH_ITEM);
     b->pop_elems = elems;
     size_t off = 0;
     b->pop_off[0] = off; off = align_up(off + elems * 4);
@@ -427,13 +454,25 @@ holb_status holb_batch_reduce(holb_batch* b, int32_t run, double out[5])
     return batch_check_flags(b);
 }
 
-static const int BATCH_VARIANTS = 3;  // 0: 4 blocks/CU, 1: reserved, 2: 8 blocks/CU
+// launch shapes: work items of 256, 512, 1024 or 2048 cells x 4, 8 or 2
+// blocks per compute unit (holb_batch::tile_of, per_cu_of)
+static const int BATCH_VARIANTS = 12;
 
 holb_status holb_batch_set_variant(holb_batch* b, int32_t variant)
 {
     if (!b) return fail(HOLB_EINVAL, "handle is NULL");
-    if (variant != 0 && variant != 2) return fail(HOLB_EUNSUPPORTED, "variant %d not available", variant);
-    if (variant != b->variant) b->drop_graphs();
+    if (variant < 0 || variant >= BATCH_VARIANTS) return fail(HOLB_EUNSUPPORTED, "variant %d not available", variant);
+    if (variant == b->variant) return HOLB_OK;
+    b->drop_graphs();
+    const int t = holb_batch::tile_of(variant);
+    if (t != b->tile) {
+        // a new work list (never longer than the one the workspace was sized for)
+        b->build_items(t);
+        hipError_t e = hipMemcpyAsync(b->ws + b->items_off, b->items.data(), b->items.size() * sizeof(int2),
+                                      hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) return hip_fail(e, "uploading the work list");
+    }
     b->variant = variant;
     return HOLB_OK;
 }
@@ -488,12 +527,15 @@ holb_status holb_batch_tune(holb_batch* b, int32_t* variant_out)
     hipError_t e = hipEventCreate(&t0);
     if (e == hipSuccess) e = hipEventCreate(&t1);
     if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
-    const int keep = b->variant;
-    int best = keep;
+    int best = b->variant;
     float best_ms = 1e30f;
     for (int v = 0; v < BATCH_VARIANTS && e == hipSuccess; ++v) {
-        if (v == 1) continue;
-        b->variant = v;
+        holb_status st = holb_batch_set_variant(b, v);
+        if (st != HOLB_OK) {
+            (void)hipEventDestroy(t0);
+            (void)hipEventDestroy(t1);
+            return st;
+        }
         // trial steps read the current buffer and write the other one
         e = b->step_once(b->stream, b->cur);
         if (e == hipSuccess) e = hipEventRecord(t0, b->stream);
@@ -506,9 +548,9 @@ holb_status holb_batch_tune(holb_batch* b, int32_t* variant_out)
     }
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
-    b->variant = keep;
     if (e != hipSuccess) return hip_fail(e, "batched tuning");
-    holb_batch_set_variant(b, best);
+    holb_status st = holb_batch_set_variant(b, best);
+    if (st != HOLB_OK) return st;
     if (variant_out) *variant_out = best;
     return HOLB_OK;
 }

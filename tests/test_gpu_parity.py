@@ -621,6 +621,44 @@ def test_batched_graph_replay_matches_eager():
             assert torch.equal(b1.fields(k)[0], b2.fields(k)[0]), (rep, k)
 
 
+def test_batched_launch_shapes_bitwise_identical():
+    """Every batched launch shape (work items of 256 to 2048 cells, 2 to 8
+    blocks per compute unit) gives bitwise identical fields, on runs that end
+    in partial items; the tuner returns one of them; shapes outside the range
+    are refused."""
+    import torch
+    from paper_2411_10751_amd import holb
+    runs = inputs.batched_runs(nruns=7, nmin=33, nmax=97, steps=5)
+    log("case batched launch shapes, sizes %s" % [r["config"]["nx"] * r["config"]["ny"] for r in runs])
+    cfgs = [r["config"] for r in runs]
+    fields = lambda r: ([x["rho"] for x in r], [x["u"] for x in r], [x["theta"] for x in r])
+    ref = None
+    for v in range(12):
+        b = holb.Batch(cfgs)
+        b.set_variant(v)
+        b.init(*fields(runs))
+        b.step(5)
+        out = [b.fields(k) for k in range(len(runs))]
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = out
+        else:
+            for k in range(len(runs)):
+                for a, c in zip(ref[k], out[k]):
+                    assert torch.equal(a, c), (v, k)
+        b.close()
+    b = holb.Batch(cfgs)
+    b.init(*fields(runs))
+    assert 0 <= b.tune() < 12
+    b.step(5)
+    for k in range(len(runs)):
+        for a, c in zip(ref[k], b.fields(k)):
+            assert torch.equal(a, c), ("tuned", k)
+    assert holb.holb_batch_set_variant(b._h, 12) == holb.EUNSUPPORTED
+    assert holb.holb_batch_set_variant(b._h, -1) == holb.EUNSUPPORTED
+    b.close()
+
+
 # ----------------------------------------------------------------- variants
 
 

@@ -205,7 +205,8 @@ holb_status holb_get_state(holb_sim* s, void* dev_dst, size_t bytes);
 holb_status holb_set_state(holb_sim* s, const void* dev_src, size_t bytes);
 
 /* Pick the fastest kernel variant for this configuration by timing each
- * candidate on trial steps that leave the state untouched; results are
+ * candidate on trial steps that leave the state untouched (the fastest of
+ * three timings of 4 steps, taken in round-robin passes); results are
  * bitwise identical across variants.  Synchronises.  variant_out may be NULL. */
 holb_status holb_tune(holb_sim* s, int32_t* variant_out);
 /* Force a kernel variant (0 = the default); HOLB_EUNSUPPORTED if it does not
@@ -251,9 +252,10 @@ holb_status holb_batch_reduce(holb_batch* b, int32_t run, double out[5]);
  * Results are bitwise identical across variants.  holb_batch_set_variant
  * uploads the work list of the new item size on the handle's stream and
  * synchronises it (HOLB_EUNSUPPORTED outside [0, 12)).  holb_batch_tune times
- * three steps of every variant (they write the idle buffer, so the state is
- * unchanged), keeps the fastest and returns it in variant_out (may be NULL);
- * it synchronises and needs holb_batch_init first (else HOLB_ESTATE). */
+ * every variant on trial steps (they write the idle buffer, so the state is
+ * unchanged; the fastest of three timings of 4 steps, taken in round-robin
+ * passes), keeps the fastest and returns it in variant_out (may be NULL); it
+ * synchronises and needs holb_batch_init first (else HOLB_ESTATE). */
 holb_status holb_batch_tune(holb_batch* b, int32_t* variant_out);
 holb_status holb_batch_set_variant(holb_batch* b, int32_t variant);
 /* Instrumentation, as holb_timing_start / holb_timing_stop: while a timing is

@@ -527,28 +527,34 @@ holb_status holb_batch_tune(holb_batch* b, int32_t* variant_out)
     hipError_t e = hipEventCreate(&t0);
     if (e == hipSuccess) e = hipEventCreate(&t1);
     if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
-    int best = b->variant;
-    float best_ms = 1e30f;
-    for (int v = 0; v < BATCH_VARIANTS && e == hipSuccess; ++v) {
-        holb_status st = holb_batch_set_variant(b, v);
-        if (st != HOLB_OK) {
-            (void)hipEventDestroy(t0);
-            (void)hipEventDestroy(t1);
-            return st;
+    // per shape the fastest of three timings of 4 steps, in round-robin passes
+    float vms[BATCH_VARIANTS];
+    for (int v = 0; v < BATCH_VARIANTS; ++v) vms[v] = 1e30f;
+    for (int pass = 0; pass < 3 && e == hipSuccess; ++pass) {
+        for (int v = 0; v < BATCH_VARIANTS && e == hipSuccess; ++v) {
+            holb_status st = holb_batch_set_variant(b, v);
+            if (st != HOLB_OK) {
+                (void)hipEventDestroy(t0);
+                (void)hipEventDestroy(t1);
+                return st;
+            }
+            // trial steps read the current buffer and write the other one
+            e = b->step_once(b->stream, b->cur);
+            if (e == hipSuccess) e = hipEventRecord(t0, b->stream);
+            for (int r = 0; r < 4 && e == hipSuccess; ++r) e = b->step_once(b->stream, b->cur);
+            if (e == hipSuccess) e = hipEventRecord(t1, b->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(t1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+            if (e == hipSuccess) vms[v] = std::min(vms[v], ms);
         }
-        // trial steps read the current buffer and write the other one
-        e = b->step_once(b->stream, b->cur);
-        if (e == hipSuccess) e = hipEventRecord(t0, b->stream);
-        for (int r = 0; r < 3 && e == hipSuccess; ++r) e = b->step_once(b->stream, b->cur);
-        if (e == hipSuccess) e = hipEventRecord(t1, b->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(t1);
-        float ms = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
-        if (e == hipSuccess && ms < best_ms) { best_ms = ms; best = v; }
     }
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
     if (e != hipSuccess) return hip_fail(e, "batched tuning");
+    int best = 0;
+    for (int v = 1; v < BATCH_VARIANTS; ++v)
+        if (vms[v] < vms[best]) best = v;
     holb_status st = holb_batch_set_variant(b, best);
     if (st != HOLB_OK) return st;
     if (variant_out) *variant_out = best;

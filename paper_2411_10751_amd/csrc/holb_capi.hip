@@ -328,24 +328,29 @@ holb_status holb_tune(holb_sim* s, int32_t* variant_out)
     hipError_t e = hipEventCreate(&t0);
     if (e == hipSuccess) e = hipEventCreate(&t1);
     if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
-    int best = s->variant;
-    float best_ms = 1e30f;
+    // Per variant the fastest of three timings of 4 steps, taken in
+    // round-robin passes so that a slow phase of the device favours none.
     const int nv = num_variants(s->base);
-    for (int v = 0; v < nv && e == hipSuccess; ++v) {
-        if (!variant_supported(s->base, v)) continue;
-        LaunchCtx c = s->ctx(true);
-        c.variant = v;
-        e = launch_step(c);  // warm-up
-        if (e != hipSuccess) break;
-        const int reps = 3;
-        e = hipEventRecord(t0, s->stream);
-        for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_step(c);
-        if (e == hipSuccess) e = hipEventRecord(t1, s->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(t1);
-        float ms = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
-        if (e == hipSuccess && ms < best_ms) { best_ms = ms; best = v; }
+    std::vector<float> vms((size_t)nv, 1e30f);
+    for (int pass = 0; pass < 3 && e == hipSuccess; ++pass) {
+        for (int v = 0; v < nv && e == hipSuccess; ++v) {
+            if (!variant_supported(s->base, v)) continue;
+            LaunchCtx c = s->ctx(true);
+            c.variant = v;
+            e = launch_step(c);  // warm-up
+            if (e != hipSuccess) break;
+            e = hipEventRecord(t0, s->stream);
+            for (int r = 0; r < 4 && e == hipSuccess; ++r) e = launch_step(c);
+            if (e == hipSuccess) e = hipEventRecord(t1, s->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(t1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+            if (e == hipSuccess) vms[(size_t)v] = std::min(vms[(size_t)v], ms);
+        }
     }
+    int best = s->variant;
+    for (int v = 0; v < nv; ++v)
+        if (vms[(size_t)v] < vms[(size_t)best]) best = v;
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
     if (e != hipSuccess) return hip_fail(e, "tuning");

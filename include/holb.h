@@ -210,7 +210,13 @@ holb_status holb_set_state(holb_sim* s, const void* dev_src, size_t bytes);
  * bitwise identical across variants.  Synchronises.  variant_out may be NULL. */
 holb_status holb_tune(holb_sim* s, int32_t* variant_out);
 /* Force a kernel variant (0 = the default); HOLB_EUNSUPPORTED if it does not
- * apply to this configuration.  holb_num_variants reports how many exist. */
+ * apply to this configuration.  holb_num_variants reports how many exist.
+ * Variants are orders in which blocks take cells (the eight XCDs receive
+ * blocks round-robin, each with its own L2): 0 cell order, 1 a contiguous
+ * eighth of the cells per XCD, 2 the chip sweeping plane by plane with each
+ * XCD taking a band of an eighth of the plane, 3, 4, 5 the same with bands of
+ * 4, 8, 16 blocks of 256 cells.  An order that does not divide the grid
+ * evenly falls back to cell order. */
 holb_status holb_set_variant(holb_sim* s, int32_t variant);
 holb_status holb_num_variants(holb_sim* s, int32_t* n);
 

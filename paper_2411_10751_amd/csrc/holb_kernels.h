@@ -242,6 +242,7 @@ struct Launch {
 
     static int nm(const KParams& p) { return L::D == 3 ? p.nz : p.ny; }
     // variant 0 cell order, 1 XCD-contiguous eighths, 2 plane bands per XCD
+    // (an eighth of a plane each), 3, 4, 5 bands of 4, 8, 16 blocks per XCD
     // (argument of xcd_block)
     static int remap(const LaunchCtx& c)
     {
@@ -250,6 +251,7 @@ struct Launch {
             const int bpp = c.kp.nlayer / GEN_BLOCK;  // blocks per plane
             return (c.kp.nlayer % GEN_BLOCK == 0 && bpp % 8 == 0) ? bpp / 8 : 0;
         }
+        if (c.variant >= 3 && c.variant <= 5) return 4 << (c.variant - 3);
         return 0;
     }
     static PlaneSet all(const KParams& p) { return PlaneSet{0, nm(p), 0, 0}; }

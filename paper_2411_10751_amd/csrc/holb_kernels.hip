@@ -48,9 +48,9 @@ void dominant_kernel(const LaunchCtx& c, char* name, size_t len, long long* cell
                  c.frames);
 }
 
-int num_variants(const LaunchCtx&) { return 3; }
+int num_variants(const LaunchCtx&) { return 6; }
 
-bool variant_supported(const LaunchCtx&, int variant) { return variant >= 0 && variant <= 2; }
+bool variant_supported(const LaunchCtx&, int variant) { return variant >= 0 && variant <= 5; }
 
 // ------------------------------------------------------- host-side tables
 

@@ -77,15 +77,21 @@ def cpu_baseline(name, storage):
             "kind": "oracle", "sample": sample + " (FP64, %.1f s)" % dt}
 
 
-def traffic_from_profile(kernel, name, storage):
+def traffic_from_profile(kernel, name, storage, variant):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the kernel source as it is now and on this kernel."""
+    was taken on the kernel source as it is now, on this kernel and in this
+    block order (the traffic depends on it)."""
+    import re
     from paper_2411_10751_amd.profile_summary import source_sha256
     path = os.path.join(ROOT, "profiles", "traffic_%s_%s.txt" % (name, {0: "f32", 1: "f16", 2: "bf16"}[storage]))
     if not os.path.exists(path):
         return None
+    lines = open(path).read().splitlines()
+    m = re.search(r"variant (\d+)", lines[0] if lines else "")
+    if m is None or int(m.group(1)) != variant:
+        return None
     vals = {}
-    for line in open(path):
+    for line in lines:
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
@@ -204,7 +210,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="rb3d", choices=["rb3d", "thermal2d", "ptensor2d", "body2d", "batched"])
     ap.add_argument("--storage", default="f32", choices=list(STORAGE))
-    ap.add_argument("--variant", type=int, default=-1, help="-1: autotune")
+    ap.add_argument("--variant", type=int, default=None,
+                    help="kernel block order; -1: autotune; default: 0 for the Rayleigh-Benard box (the order "
+                         "its rocprofv3 summaries were taken in, and the one the tuner picks there), "
+                         "autotuned for the other workloads")
     ap.add_argument("--frames", default="auto", choices=["auto", "cell", "plane", "cellu"],
                     help="reference frames of the stored populations")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -256,6 +265,8 @@ def main():
         for v in sorted(best):
             print("variant %d: %.4f ms/step" % (v, best[v]), file=sys.stderr, flush=True)
         sim.init(w["rho"], w["u"], w["theta"])
+    if args.variant is None:
+        args.variant = 0 if args.workload == "rb3d" else -1
     if args.variant >= 0:
         sim.set_variant(args.variant)
         variant = args.variant
@@ -291,7 +302,7 @@ def main():
     mlups = cells / (step_ms * 1e-3) / 1e6
     bpc = 2 * Q * STORE_BYTES[storage]  # read + write every population once
     achieved = bpc * kcells / (kern_ms * 1e-3) / 1e9
-    traffic = traffic_from_profile(kernel, args.workload, storage)
+    traffic = traffic_from_profile(kernel, args.workload, storage, variant)
     line = {
         "metric": METRIC,
         "value": round(mlups, 2),

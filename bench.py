@@ -103,6 +103,17 @@ def traffic_from_profile(kernel, name, storage, variant):
         return None
 
 
+def copy_calibration(torch):
+    """The reference dispatch that scales the profiler's byte counters: an
+    elementwise negation of 2^28 float32 (1 GiB in, 1 GiB out), three times."""
+    a = torch.zeros(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    del a, b
+
+
 def bench_batched(args):
     """512 independent D2Q37 body-force + thermal runs (sizes 32^2..256^2,
     uneven parameters) advanced together by the batched form, FP32."""
@@ -113,7 +124,11 @@ def bench_batched(args):
     torch.cuda.set_device(0)
     b = holb.Batch([r["config"] for r in runs])
     b.init([r["rho"] for r in runs], [r["u"] for r in runs], [r["theta"] for r in runs])
-    variant = b.tune()
+    if args.variant is not None and args.variant >= 0:
+        b.set_variant(args.variant)
+        variant = args.variant
+    else:
+        variant = b.tune()
     b.step(args.warmup)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -159,8 +174,11 @@ def bench_batched(args):
     single_ms = s0.elapsed_time(s1) / single_steps
     for sm in sims:
         sm.close()
+    if args.copy_calibration:
+        copy_calibration(torch)
     bpc = 2 * 37 * 4
     achieved = bpc * kcells / (kern_ms * 1e-3) / 1e9
+    traffic = traffic_from_profile(kernel, "batched", 0, variant)
     line = {
         "metric": METRIC,
         "value": round(cells / (step_ms * 1e-3) / 1e6, 2),
@@ -180,7 +198,7 @@ def bench_batched(args):
                    "one_run_at_a_time_ms_per_step": round(single_ms, 5),
                    "one_run_at_a_time_mlups": round(cells / (single_ms * 1e-3) / 1e6, 2)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kernel,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel,
                      "kernel_ms": round(kern_ms, 5), "cells_per_launch": kcells, "alg_bytes_per_cell": bpc},
     }
     if not args.no_cpu_baseline:
@@ -211,9 +229,9 @@ def main():
     ap.add_argument("--workload", default="rb3d", choices=["rb3d", "thermal2d", "ptensor2d", "body2d", "batched"])
     ap.add_argument("--storage", default="f32", choices=list(STORAGE))
     ap.add_argument("--variant", type=int, default=None,
-                    help="kernel block order; -1: autotune; default: 0 for the Rayleigh-Benard box (the order "
-                         "its rocprofv3 summaries were taken in, and the one the tuner picks there), "
-                         "autotuned for the other workloads")
+                    help="kernel block order (for the batched workload: its launch shape); -1: autotune; "
+                         "default: 0 for the Rayleigh-Benard box (the order its rocprofv3 summaries were taken "
+                         "in, and the one the tuner picks there), autotuned for the other workloads")
     ap.add_argument("--frames", default="auto", choices=["auto", "cell", "plane", "cellu"],
                     help="reference frames of the stored populations")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -292,12 +310,7 @@ def main():
     kern_ms /= max(launches, 1)
 
     if args.copy_calibration:
-        a = torch.zeros(1 << 28, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        for _ in range(3):
-            torch.neg(a, out=b)
-        torch.cuda.synchronize()
-        del a, b
+        copy_calibration(torch)
 
     mlups = cells / (step_ms * 1e-3) / 1e6
     bpc = 2 * Q * STORE_BYTES[storage]  # read + write every population once

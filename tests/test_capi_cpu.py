@@ -237,3 +237,34 @@ int main() {
     subprocess.run(["g++", "-O2", str(src), "-o", str(exe)], check=True)
     r = subprocess.run([str(exe)], capture_output=True, text=True)
     assert r.returncode == 0 and r.stdout.split()[0] == "0", r.stdout
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU: asked for more it exits with status 2 and
+    says so, before touching a device."""
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_bench_traffic_needs_matching_profile(tmp_path, monkeypatch):
+    """bench.py reports the profiled HBM traffic only for the kernel, block
+    order and kernel sources its counter summary records."""
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_2411_10751_amd.profile_summary import source_sha256
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    (prof / "traffic_rb3d_f32.txt").write_text(
+        "# HBM traffic per launch of the dominant kernel, test, variant 3\n"
+        "kernel: k_step<D3Q39,0,1,false,1>\nsource_sha256: %s\nhbm_bytes_per_launch: 1234\n" % source_sha256())
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.traffic_from_profile("k_step<D3Q39,0,1,false,1>", "rb3d", 0, 3) == 1234.0
+    assert bench.traffic_from_profile("k_step<D3Q39,0,1,false,1>", "rb3d", 0, 0) is None
+    assert bench.traffic_from_profile("k_aux<D3Q39,0,1,false,1>", "rb3d", 0, 3) is None
+    assert bench.traffic_from_profile("k_step<D3Q39,0,1,false,1>", "rb3d", 1, 3) is None
+    (prof / "traffic_rb3d_f32.txt").write_text(
+        "# title, variant 3\nkernel: k_step<D3Q39,0,1,false,1>\nsource_sha256: 0\nhbm_bytes_per_launch: 1\n")
+    assert bench.traffic_from_profile("k_step<D3Q39,0,1,false,1>", "rb3d", 0, 3) is None

@@ -8,7 +8,8 @@
  *
  * State is the shifted, pre-collision population f^ of Eq. (4.3).  One step
  * follows the order the paper's update implies:
- *   1. wall closure of the unknown populations (Section 4.3, Eqs. 4.7-4.8),
+ *   1. wall closure of the unknown populations (Section 4.3, Eqs. 4.7-4.8;
+ *      the wall-node target solved from the boundary conditions),
  *   2. moments and macroscopic fields with the source shift (Eq. 4.5),
  *      including the pseudopotential force (Eq. 3.8) when enabled,
  *   3. temperature gradient by central finite differences (Section 3.2),
@@ -431,6 +432,8 @@ struct orc_sim {
     double *gradT;          /* [3][N] */
     double *jmom, *emom;    /* first moment [3][N] and energy moment [N] */
     double *trho, *tu, *ttheta; /* TMS targets: previous-step fields */
+    long ncol;              /* cells per wall-normal layer */
+    double *lost;           /* [2][ncol]: mass that left through each wall, per column, at the last streaming */
 };
 
 static void *xcalloc(long n, size_t sz)
@@ -443,7 +446,7 @@ void orc_destroy(orc_sim *s)
     if (!s) return;
     free(s->f); free(s->fpost); free(s->rho); free(s->u); free(s->theta); free(s->force);
     free(s->psi); free(s->Fsc); free(s->gradT); free(s->trho); free(s->tu); free(s->ttheta);
-    free(s->jmom); free(s->emom);
+    free(s->jmom); free(s->emom); free(s->lost);
     free(s);
 }
 
@@ -494,7 +497,9 @@ int orc_create(const orc_config *cfg, orc_sim **out)
     s->ttheta = xcalloc(N, sizeof(double));
     s->jmom = xcalloc(3 * N, sizeof(double));
     s->emom = xcalloc(N, sizeof(double));
-    if (!s->jmom || !s->emom ||
+    s->ncol = N / s->dims[s->wax];
+    s->lost = xcalloc(2 * s->ncol, sizeof(double));
+    if (!s->jmom || !s->emom || !s->lost ||
         !s->f || !s->fpost || !s->rho || !s->u || !s->theta || !s->force || !s->psi || !s->Fsc ||
         !s->gradT || !s->trho || !s->tu || !s->ttheta) {
         orc_destroy(s);
@@ -516,6 +521,8 @@ static long cell_of(const orc_sim *s, const long x[3])
     return x[0] + s->dims[0] * (x[1] + (long)s->dims[1] * x[2]);
 }
 
+static void wall_outflow(orc_sim *s, const double *fp);
+
 /* Initial state f^0 = f^eq(rho, u, theta) (Section 5 initial fields). */
 int orc_init(orc_sim *s, const double *rho, const double *u, const double *theta)
 {
@@ -535,77 +542,259 @@ int orc_init(orc_sim *s, const double *rho, const double *u, const double *theta
         for (int a = 0; a < 3; ++a) s->tu[a * N + cell] = uu[a];
         s->ttheta[cell] = th;
     }
-    return bad ? ORC_EINVAL : ORC_OK;
+    if (bad) return ORC_EINVAL;
+    /* Before the first step no population has left yet; the wall closure of
+     * step 0 balances the mass the initial equilibrium would send out, as if
+     * it were the post-collision state of a step before. */
+    wall_outflow(s, s->f);
+    return ORC_OK;
 }
 
-/* Section 4.3, Eqs. (4.7)-(4.8): the populations streamed in from outside the
- * domain (unknown set U) are rebuilt as f_i = f_ibar + f^eq_i(tgt) - f^eq_ibar(loc),
- * i.e. the target equilibrium plus the non-equilibrium part of the opposite
- * population; the local state fills U with the target equilibrium.  The
- * opposite index on the local equilibrium is the reading under which a node
- * already at the target state is left unchanged and a moving wall imposes its
- * velocity (the Couette validation of Section 5.1); with the index i on both
- * equilibria the unknowns reduce to plain bounce-back at that state.  Targets:
- * wall nodes (first and last layer along the wall-normal axis) lie outside
- * the fluid, and their targets come from the boundary condition holding
- * half-way between them and the first fluid layer: the reflection
- * 2 u_wall - u_1 and 2 theta_wall - theta_1 of that layer's previous-step
- * fields, with the node's own previous-step density.  The fluid between the
- * walls is then n - 2 nodes high (Sections 5.1 and 5.2: 54 of 56).  Fluid
- * nodes take their own previous-step fields. */
-static void tms_fill(orc_sim *s)
+/* Mass that leaves the domain through each wall in the streaming of the
+ * post-collision state fp: for every column along the wall-normal axis, the
+ * populations of its first three nodes next to the wall that point out of the
+ * domain (summed in node order, then velocity order). */
+static void wall_outflow(orc_sim *s, const double *fp)
 {
     if (!s->cfg.walls) return;
     const orc_lattice *L = s->L;
-    long N = s->N;
+    long N = s->N, ncol = s->ncol;
     int nax = s->dims[s->wax];
-#ifdef _OPENMP
-#pragma omp parallel for schedule(static)
-#endif
-    for (long cell = 0; cell < N; ++cell) {
-        long x[3];
-        coords(s, cell, x);
-        long k = x[s->wax];
-        int unknown[ORC_QMAX], nun = 0;
-        for (int i = 0; i < L->Q; ++i) {
-            long src = k - L->c[i][s->wax];
-            unknown[i] = (src < 0 || src >= nax);
-            nun += unknown[i];
+    for (long col = 0; col < ncol; ++col)
+        for (int wall = 0; wall < 2; ++wall) {
+            double m = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                long k = wall == 0 ? d : nax - 1 - d;
+                long cell = col + k * ncol;
+                for (int i = 0; i < L->Q; ++i) {
+                    long dst = k + L->c[i][s->wax];
+                    if (dst < 0 || dst >= nax) m += fp[i * N + cell];
+                }
+            }
+            s->lost[wall * ncol + col] = m;
         }
-        if (!nun) continue;
-        double rt = s->trho[cell], ut[3], tt;
-        int wall = (k == 0) ? 0 : (k == nax - 1) ? 1 : -1;
-        if (wall >= 0) {
-            long xn[3] = {x[0], x[1], x[2]};
-            xn[s->wax] = wall == 0 ? 1 : nax - 2;
-            long c1 = cell_of(s, xn);
-            for (int a = 0; a < 3; ++a) ut[a] = a < s->D ? 2.0 * s->cfg.u_wall[wall][a] - s->tu[a * N + c1] : 0.0;
-            tt = 2.0 * s->cfg.theta_wall[wall] - s->ttheta[c1];
-        } else {
-            for (int a = 0; a < 3; ++a) ut[a] = s->tu[a * N + cell];
-            tt = s->ttheta[cell];
-        }
-        if (s->cfg.isothermal) tt = 1.0;
-        double fet[ORC_QMAX], fel[ORC_QMAX];
-        orc_feq(s->cfg.lattice, rt, ut, tt, fet);
-        double rl = 0, jl[3] = {0, 0, 0}, el = 0;
-        for (int i = 0; i < L->Q; ++i) {
-            double fi = unknown[i] ? fet[i] : s->f[i * N + cell];
-            rl += fi;
-            for (int a = 0; a < 3; ++a) jl[a] += fi * L->c[i][a];
-            el += fi * (L->c[i][0] * L->c[i][0] + L->c[i][1] * L->c[i][1] + L->c[i][2] * L->c[i][2]);
-        }
-        double Fl[3], ul[3];
-        for (int a = 0; a < 3; ++a) {
-            Fl[a] = (s->cfg.sources & ORC_SRC_BODY) ? rl * s->cfg.g[a] : 0.0;
-            if (a >= s->D) Fl[a] = 0.0;
-            ul[a] = (jl[a] + 0.5 * Fl[a]) / rl;
-        }
-        double tl = s->cfg.isothermal ? 1.0 : (el - rl * dot3(ul, ul) + dot3(ul, Fl)) / (rl * s->D * L->c0sq);
-        orc_feq(s->cfg.lattice, rl, ul, tl, fel);
-        for (int i = 0; i < L->Q; ++i)
-            if (unknown[i]) s->f[i * N + cell] = s->f[L->opp[i] * N + cell] + fet[i] - fel[L->opp[i]];
+}
+
+/* Eq. (4.7) at one boundary node: the unknown populations (bit set in unknown)
+ * become f_i = f_ibar + f^eq_i(tgt) - f^eq_ibar(loc), where loc is the state of
+ * Eq. (4.8): the known populations plus the target equilibrium in the unknown
+ * slots, with the shifted velocity (rho u = sum c f + F/2, F = rho g) and the
+ * temperature of Eq. (4.5).  The local equilibrium is taken at the opposite
+ * index (non-equilibrium bounce-back): a node already at the target state is
+ * left unchanged, and a moving wall imposes its velocity (Section 5.1); with
+ * the index i on both equilibria the unknowns reduce to plain bounce-back at
+ * that state.  The node's populations f[Q] are read and the result written to
+ * out[Q]; the mass of the rebuilt populations is returned. */
+static double tms_node(const orc_sim *s, const double *f, const int *unknown, double rt, const double ut[3],
+                       double tt, double *out)
+{
+    const orc_lattice *L = s->L;
+    if (s->cfg.isothermal) tt = 1.0;
+    double fet[ORC_QMAX], fel[ORC_QMAX];
+    orc_feq(s->cfg.lattice, rt, ut, tt, fet);
+    double rl = 0, jl[3] = {0, 0, 0}, el = 0;
+    for (int i = 0; i < L->Q; ++i) {
+        double fi = unknown[i] ? fet[i] : f[i];
+        rl += fi;
+        for (int a = 0; a < 3; ++a) jl[a] += fi * L->c[i][a];
+        el += fi * (L->c[i][0] * L->c[i][0] + L->c[i][1] * L->c[i][1] + L->c[i][2] * L->c[i][2]);
     }
+    double Fl[3], ul[3];
+    for (int a = 0; a < 3; ++a) {
+        Fl[a] = ((s->cfg.sources & ORC_SRC_BODY) && a < s->D) ? rl * s->cfg.g[a] : 0.0;
+        ul[a] = (jl[a] + 0.5 * Fl[a]) / rl;
+    }
+    double tl = s->cfg.isothermal ? 1.0 : (el - rl * dot3(ul, ul) + dot3(ul, Fl)) / (rl * s->D * L->c0sq);
+    orc_feq(s->cfg.lattice, rl, ul, tl, fel);
+    double m = 0.0;
+    for (int i = 0; i < L->Q; ++i) {
+        out[i] = unknown[i] ? f[L->opp[i]] + fet[i] - fel[L->opp[i]] : f[i];
+        if (unknown[i]) m += out[i];
+    }
+    return m;
+}
+
+/* Macroscopic state of Eq. (4.5) of one node's populations f[Q]. */
+static void node_macro(const orc_sim *s, const double *f, double *rho, double u[3], double *theta)
+{
+    const orc_lattice *L = s->L;
+    double r = 0, j[3] = {0, 0, 0}, e = 0;
+    for (int i = 0; i < L->Q; ++i) {
+        r += f[i];
+        for (int a = 0; a < 3; ++a) j[a] += f[i] * L->c[i][a];
+        e += f[i] * (L->c[i][0] * L->c[i][0] + L->c[i][1] * L->c[i][1] + L->c[i][2] * L->c[i][2]);
+    }
+    double F[3];
+    for (int a = 0; a < 3; ++a) {
+        F[a] = ((s->cfg.sources & ORC_SRC_BODY) && a < s->D) ? r * s->cfg.g[a] : 0.0;
+        u[a] = (j[a] + 0.5 * F[a]) / r;
+    }
+    *rho = r;
+    *theta = s->cfg.isothermal ? 1.0 : (e - r * dot3(u, u) + dot3(u, F)) / (r * s->D * L->c0sq);
+}
+
+/* Unknown set of the node at wall-normal index k: the populations whose
+ * source node x - c_i lies outside the domain.  Returns their number. */
+static int unknown_set(const orc_sim *s, long k, int *unknown)
+{
+    int n = 0, nax = s->dims[s->wax];
+    for (int i = 0; i < s->L->Q; ++i) {
+        long src = k - s->L->c[i][s->wax];
+        unknown[i] = (src < 0 || src >= nax);
+        n += unknown[i];
+    }
+    return n;
+}
+
+/* Target of a wall node (Section 4.3: computed from the boundary condition).
+ * The wall node lies outside the fluid, half-way across the wall from the
+ * first fluid node, so the boundary values hold half-way between the two:
+ *   - impermeability: the populations the closure rebuilds along this column
+ *     (wall node and fluid boundary nodes) carry exactly the mass that left
+ *     through the wall in the last streaming, which fixes rho_tgt;
+ *   - no slip and the wall temperature: after the closure the wall node holds
+ *     the reflection 2 u_wall - u_1 (components along the wall) and
+ *     2 theta_wall - theta_1 of the first fluid node's previous-step fields,
+ *     which fixes the tangential u_tgt and theta_tgt;
+ *   - the wall-normal u_tgt is the reflection itself.
+ * These conditions (D + 1 equations; D in the isothermal mode) are solved by
+ * Newton's method with a finite-difference Jacobian, started from the node's
+ * previous-step density and the reflected fields.  v = (rho, tangential u,
+ * theta) in that order. */
+static int wall_target(const orc_sim *s, const double *f, const int *unknown, double mass_want,
+                       const double udes[3], double thdes, double rprev, double rt_out[1], double ut_out[3],
+                       double *tt_out)
+{
+    const int D = s->D, wax = s->wax;
+    int idx[5], nv = 0; /* -1: rho, 0..2: u component, 3: theta */
+    idx[nv++] = -1;
+    for (int a = 0; a < D; ++a)
+        if (a != wax) idx[nv++] = a;
+    if (!s->cfg.isothermal) idx[nv++] = 3;
+    double v[5];
+    for (int q = 0; q < nv; ++q) v[q] = idx[q] == -1 ? rprev : idx[q] == 3 ? thdes : udes[idx[q]];
+    double out[ORC_QMAX];
+    for (int it = 0; it < 60; ++it) {
+        double R[5], J[5][5];
+        for (int col = -1; col < nv; ++col) {
+            double vv[5];
+            memcpy(vv, v, sizeof vv);
+            double h = 0.0;
+            if (col >= 0) {
+                h = 1e-7 * (fabs(v[col]) + (idx[col] == -1 || idx[col] == 3 ? 0.0 : 1e-2));
+                vv[col] += h;
+            }
+            double rt = rprev, ut[3] = {udes[0], udes[1], udes[2]}, tt = thdes;
+            for (int q = 0; q < nv; ++q) {
+                if (idx[q] == -1) rt = vv[q];
+                else if (idx[q] == 3) tt = vv[q];
+                else ut[idx[q]] = vv[q];
+            }
+            double m = tms_node(s, f, unknown, rt, ut, tt, out);
+            double ra, ua[3], tha;
+            node_macro(s, out, &ra, ua, &tha);
+            double res[5];
+            for (int q = 0; q < nv; ++q)
+                res[q] = idx[q] == -1 ? m - mass_want : idx[q] == 3 ? tha - thdes : ua[idx[q]] - udes[idx[q]];
+            if (col < 0) memcpy(R, res, sizeof R);
+            else for (int q = 0; q < nv; ++q) J[q][col] = (res[q] - R[q]) / h;
+        }
+        /* J dv = -R by Gaussian elimination with partial pivoting */
+        double A[5][6], dv[5];
+        for (int q = 0; q < nv; ++q) {
+            for (int c = 0; c < nv; ++c) A[q][c] = J[q][c];
+            A[q][nv] = -R[q];
+        }
+        for (int k = 0; k < nv; ++k) {
+            int piv = k;
+            for (int q = k + 1; q < nv; ++q)
+                if (fabs(A[q][k]) > fabs(A[piv][k])) piv = q;
+            for (int c = 0; c <= nv; ++c) { double t = A[k][c]; A[k][c] = A[piv][c]; A[piv][c] = t; }
+            if (A[k][k] == 0.0) return ORC_ENUMERIC;
+            for (int q = k + 1; q < nv; ++q) {
+                double fct = A[q][k] / A[k][k];
+                for (int c = k; c <= nv; ++c) A[q][c] -= fct * A[k][c];
+            }
+        }
+        for (int k = nv - 1; k >= 0; --k) {
+            double acc = A[k][nv];
+            for (int c = k + 1; c < nv; ++c) acc -= A[k][c] * dv[c];
+            dv[k] = acc / A[k][k];
+        }
+        int done = 1;
+        for (int q = 0; q < nv; ++q) {
+            v[q] += dv[q];
+            if (!isfinite(v[q])) return ORC_ENUMERIC;
+            if (fabs(dv[q]) > 1e-14 * (1.0 + fabs(v[q]))) done = 0;
+        }
+        if (done) {
+            rt_out[0] = rprev;
+            for (int a = 0; a < 3; ++a) ut_out[a] = udes[a];
+            *tt_out = thdes;
+            for (int q = 0; q < nv; ++q) {
+                if (idx[q] == -1) rt_out[0] = v[q];
+                else if (idx[q] == 3) *tt_out = v[q];
+                else ut_out[idx[q]] = v[q];
+            }
+            return ORC_OK;
+        }
+    }
+    return ORC_ENUMERIC;
+}
+
+/* Section 4.3, Eqs. (4.7)-(4.8): TMS closure of the populations streamed in
+ * from outside the walls.  Boundary nodes are the first three layers next to
+ * each wall (the lattice reaches three nodes).  The first layer holds the
+ * wall nodes, outside the fluid: the wall lies half-way between them and the
+ * first fluid layer, so the fluid between the walls is n - 2 nodes high
+ * (Sections 5.1 and 5.2: 54 of 56).  Fluid boundary nodes (second and third
+ * layers) target their own previous-step fields; wall nodes take the target
+ * that the boundary conditions fix (wall_target).  Per column, the fluid
+ * boundary nodes are closed first, because the wall node's mass balance
+ * counts what they rebuild. */
+static int tms_fill(orc_sim *s)
+{
+    if (!s->cfg.walls) return ORC_OK;
+    const orc_lattice *L = s->L;
+    long N = s->N, ncol = s->ncol;
+    int nax = s->dims[s->wax], D = s->D;
+    int bad = 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) reduction(| : bad)
+#endif
+    for (long col = 0; col < ncol; ++col) {
+        for (int wall = 0; wall < 2; ++wall) {
+            double f[ORC_QMAX], out[ORC_QMAX];
+            int unknown[ORC_QMAX];
+            double mass_fluid = 0.0;
+            for (int d = 1; d < 3; ++d) {
+                long k = wall == 0 ? d : nax - 1 - d;
+                long cell = col + k * ncol;
+                if (!unknown_set(s, k, unknown)) continue;
+                for (int i = 0; i < L->Q; ++i) f[i] = s->f[i * N + cell];
+                double ut[3] = {s->tu[cell], s->tu[N + cell], s->tu[2 * N + cell]};
+                mass_fluid += tms_node(s, f, unknown, s->trho[cell], ut, s->ttheta[cell], out);
+                for (int i = 0; i < L->Q; ++i) s->f[i * N + cell] = out[i];
+            }
+            long k = wall == 0 ? 0 : nax - 1;
+            long cell = col + k * ncol;
+            long c1 = col + (wall == 0 ? 1 : nax - 2) * ncol;
+            unknown_set(s, k, unknown);
+            for (int i = 0; i < L->Q; ++i) f[i] = s->f[i * N + cell];
+            double udes[3] = {0, 0, 0};
+            for (int a = 0; a < D; ++a) udes[a] = 2.0 * s->cfg.u_wall[wall][a] - s->tu[a * N + c1];
+            double thdes = s->cfg.isothermal ? 1.0 : 2.0 * s->cfg.theta_wall[wall] - s->ttheta[c1];
+            double rt, ut[3], tt;
+            if (wall_target(s, f, unknown, s->lost[wall * ncol + col] - mass_fluid, udes, thdes, s->trho[cell],
+                            &rt, ut, &tt)) {
+                bad = 1;
+                continue;
+            }
+            tms_node(s, f, unknown, rt, ut, tt, out);
+            for (int i = 0; i < L->Q; ++i) s->f[i * N + cell] = out[i];
+        }
+    }
+    return bad ? ORC_ENUMERIC : ORC_OK;
 }
 
 /* Eq. (4.5): rho = F^_0, rho u = F^_1 + F/2 (G_1 = F exactly), and
@@ -770,8 +959,9 @@ static void stream(orc_sim *s, const double *fpost)
 
 static int stages_to_collision(orc_sim *s)
 {
-    tms_fill(s);
-    int rc = macroscopic(s);
+    int rc = tms_fill(s);
+    if (rc) return rc;
+    rc = macroscopic(s);
     if (rc) return rc;
     if (s->cfg.sources & ORC_SRC_THERMAL) grad_theta(s);
     else memset(s->gradT, 0, sizeof(double) * 3 * s->N);
@@ -788,6 +978,7 @@ int orc_step(orc_sim *s, int nsteps)
             memcpy(s->trho, s->rho, sizeof(double) * s->N);
             memcpy(s->tu, s->u, sizeof(double) * 3 * s->N);
             memcpy(s->ttheta, s->theta, sizeof(double) * s->N);
+            wall_outflow(s, s->fpost);
         }
         stream(s, s->fpost);
     }

@@ -89,6 +89,8 @@ int orc_init(orc_sim *s, const double *rho, const double *u, const double *theta
 int orc_step(orc_sim *s, int nsteps);
 int orc_fields(orc_sim *s, double *rho, double *u, double *theta);
 int orc_reduce(orc_sim *s, double out[5]);
+/* The populations f[Q*N] only: with walls, the previous-step targets and the
+ * mass that left through each wall stay as they are. */
 int orc_get_state(orc_sim *s, double *f);
 int orc_set_state(orc_sim *s, const double *f);
 int orc_collide_only(orc_sim *s, double *fpost);

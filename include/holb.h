@@ -62,10 +62,10 @@ typedef int32_t holb_status;
 #define HOLB_SRC_THERMAL 2u /* thermal-dissipation source H_i, Eq. (3.7) */
 #define HOLB_SRC_PTENSOR 4u /* pseudopotential force (Eq. 3.8) + P_i (Eq. 3.12) */
 
-/* Population storage in device memory.  Arithmetic is always FP32.  Every
- * cell carries a frame (its density and temperature of the last step, rounded
- * to binary16), and populations are stored as deviations from the rest
- * equilibrium of their cell's frame, divided by w_i.  The 16-bit forms also
+/* Population storage in device memory.  Arithmetic is always FP32.
+ * Populations are stored as deviations, divided by w_i, from the rest
+ * equilibrium of a frame (a density and temperature): the frame of their cell
+ * or of their plane, per the frame mode below.  The 16-bit forms also
  * subtract the bracket of the uniform background velocity u0 and round to
  * nearest-even (see holb_get_state for the exact format). */
 /* Frames (the reference the stored populations are deviations from, see
@@ -101,6 +101,7 @@ typedef int32_t holb_status;
 #define HOLB_ERR_DENSITY 1u  /* rho <= 0 or not finite */
 #define HOLB_ERR_THETA 2u    /* theta <= 0 or not finite */
 #define HOLB_ERR_EOS 4u      /* psi^2 < 0 or b rho >= 1 in the equation of state */
+#define HOLB_ERR_WALL 8u     /* the wall-node target of the TMS closure did not converge */
 
 typedef struct {
     int32_t abi_version;  /* must equal HOLB_ABI_VERSION */
@@ -119,7 +120,13 @@ typedef struct {
     double rho0, theta0, u0[3]; /* background state: u0 (with rho0, theta0) centres the 16-bit
                                  * storage; theta0 is the offset of the temperature field of
                                  * the gradient stencil */
-    int32_t walls;        /* 0: periodic; 1: TMS walls (Eqs. 4.7-4.8) normal to the last axis */
+    int32_t walls;        /* 0: periodic; 1: TMS walls (Section 4.3, Eqs. 4.7-4.8) normal to the
+                           * last axis.  The first and last layers hold the wall nodes, outside the
+                           * fluid; each wall lies half-way between them and the next layer, so the
+                           * fluid is n - 2 nodes high.  A wall node's target is solved from the
+                           * wall's boundary conditions: no net mass through the wall, and after the
+                           * closure the node holds the reflection of the first fluid node's
+                           * tangential velocity and temperature about the wall values. */
     double theta_wall[2]; /* wall temperatures: [0] at index 0, [1] at index n-1 */
     double u_wall[2][3];  /* wall velocities, same order */
     int32_t frames;       /* HOLB_FRAMES_*: reference of the stored populations */
@@ -164,7 +171,8 @@ holb_status holb_step(holb_sim* s, int64_t n);
  * returns HOLB_ENUMERIC if the device error flags are set. */
 holb_status holb_fields(holb_sim* s, float* rho, float* u, float* theta);
 
-/* Global FP64 totals of the current state into host out[5]: mass sum rho,
+/* Global FP64 totals of the current state (the conserved moments of Eq. 2.3,
+ * with the macroscopic fields of Eq. 4.5) into host out[5]: mass sum rho,
  * momentum sum rho u (x, y, z; z = 0 in 2D), energy
  * sum (rho |u|^2 + rho D c0^2 theta) / 2.  Deterministic order.  Synchronises;
  * returns HOLB_ENUMERIC if the device error flags are set. */
@@ -189,8 +197,12 @@ holb_status holb_error_flags(holb_sim* s, uint32_t* flags);
  * With walls, the wall targets follow (again 256-byte aligned): for the
  * three layers next to each wall (layer k = 0, 1, 2 from the low wall, then
  * n-3, n-2, n-1), the last step's rho, u[D] and theta, each a plane of the
- * layer's cells (float).  Restoring them makes a resumed walled run
- * continue bitwise as the uninterrupted one.  holb_set_state needs no
+ * layer's cells (float); then, for the low and the high wall, the wall-node
+ * target the last step solved (rho, u[D], theta, planes of the layer's cells:
+ * the starting point of the next solve).  Restoring them makes a resumed
+ * walled run continue bitwise as the uninterrupted one.  Slots of the first
+ * three layers whose population would leave through a wall are pulled by no
+ * node: they hold the outflow whose mass the next closure gives back.  holb_set_state needs no
  * holb_init before it and clears the device error flags.
  * Slot i of cell y holds the post-collision population f*_i(y) of the last
  * step in the frame F of y: h = f*_i / w_i - rho_F (1 + t_i(u = 0, theta_F))

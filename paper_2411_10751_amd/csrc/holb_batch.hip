@@ -60,7 +60,7 @@ __device__ __forceinline__ KParams run_params(const RunDesc& r, unsigned* err, c
 template <int FAM>
 __global__ void __launch_bounds__(BATCH_ITEM)
 k_batch_aux(const RunDesc* __restrict__ runs, const int2* __restrict__ items, int nitems, int tile,
-            const float* __restrict__ fin, float* __restrict__ aux, const float* __restrict__ tgi, unsigned* err,
+            const float* __restrict__ fin, float* __restrict__ aux, const double* __restrict__ tgi, unsigned* err,
             const float* __restrict__ tab)
 {
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
@@ -82,7 +82,7 @@ template <int FAM>
 __global__ void __launch_bounds__(BATCH_ITEM)
 k_batch_step(const RunDesc* __restrict__ runs, const int2* __restrict__ items, int nitems, int tile,
              const float* __restrict__ fin, float* __restrict__ fout, const float* __restrict__ aux,
-             const double* __restrict__ auxd, const float* __restrict__ tgi, float* __restrict__ tgo, unsigned* err,
+             const double* __restrict__ auxd, const double* __restrict__ tgi, double* __restrict__ tgo, unsigned* err,
              const float* __restrict__ tab)
 {
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
@@ -177,7 +177,7 @@ struct holb_batch {
         float* fout = pop(1 - from);
         if (fam == FAM_THERMAL) {
             hipLaunchKernelGGL(k_batch_aux<FAM_THERMAL>, dim3(grid()), dim3(BATCH_ITEM), 0, s, d_runs(), d_items(),
-                               nit, tile, fin, aux(), (const float*)nullptr, err(), (const float*)tab());
+                               nit, tile, fin, aux(), (const double*)nullptr, err(), (const float*)tab());
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
@@ -188,11 +188,11 @@ struct holb_batch {
         if (fam == FAM_THERMAL)
             hipLaunchKernelGGL(k_batch_step<FAM_THERMAL>, dim3(grid()), dim3(BATCH_ITEM), 0, s, d_runs(),
                                d_items(), nit, tile, fin, fout, (const float*)aux(), (const double*)nullptr,
-                               (const float*)nullptr, (float*)nullptr, err(), (const float*)tab());
+                               (const double*)nullptr, (double*)nullptr, err(), (const float*)tab());
         else
             hipLaunchKernelGGL(k_batch_step<FAM_LOCAL>, dim3(grid()), dim3(BATCH_ITEM), 0, s, d_runs(), d_items(),
-                               nit, tile, fin, fout, (const float*)aux(), (const double*)nullptr, (const float*)nullptr,
-                               (float*)nullptr, err(), (const float*)tab());
+                               nit, tile, fin, fout, (const float*)aux(), (const double*)nullptr, (const double*)nullptr,
+                               (double*)nullptr, err(), (const float*)tab());
         hipError_t e = hipGetLastError();
         if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
         return e;

@@ -34,6 +34,7 @@ struct Layout {
     size_t aux_off = 0, aux_bytes = 0;
     size_t tgt_off[2] = {0, 0};
     size_t tgt_bytes = 0;
+    size_t wall_off = 0, wall_bytes = 0;  // solved wall-node targets and fluid-layer masses (FP64)
     size_t part_off = 0;
     int max_partials = 0;
     size_t out_off = 0;
@@ -66,10 +67,12 @@ Layout layout_of(const holb_config* c)
     L.aux_off = off; off = align_up(off + L.aux_bytes);
     if (c->walls) {
         const size_t nlayer = D == 2 ? (size_t)c->nx : (size_t)c->nx * c->ny;
-        L.tgt_bytes = 6 * (size_t)(D + 2) * nlayer * sizeof(float);
+        L.tgt_bytes = TGT_SLOTS * (size_t)(D + 2) * nlayer * sizeof(double);
+        L.wall_bytes = (2 * 5 + 2 * 2) * nlayer * sizeof(double);
     }
     L.tgt_off[0] = off; off = align_up(off + L.tgt_bytes);
     L.tgt_off[1] = off; off = align_up(off + L.tgt_bytes);
+    L.wall_off = off; off = align_up(off + L.wall_bytes);
     L.max_partials = (int)((N + 255) / 256);
     L.part_off = off; off = align_up(off + (size_t)L.max_partials * 5 * sizeof(double));
     L.out_off = off; off = align_up(off + 8 * sizeof(double));
@@ -106,8 +109,8 @@ struct holb_sim {
         const int nxt = 1 - cur;
         c.pop_in = ws + lay.pop_off[cur];
         c.pop_out = ws + lay.pop_off[nxt];
-        c.tgt_in = (const float*)(ws + lay.tgt_off[cur]);
-        c.tgt_out = (float*)(ws + lay.tgt_off[advance ? nxt : cur]);
+        c.tgt_in = (const double*)(ws + lay.tgt_off[cur]);
+        c.tgt_out = (double*)(ws + lay.tgt_off[advance ? nxt : cur]);
         c.variant = variant;
         return c;
     }
@@ -168,6 +171,11 @@ holb_status holb_create(const holb_config* cfg, void* dev_workspace, size_t byte
         c.kp.plane_frame = (const float*)(h->ws + L.tab_off);
         c.kp.plane_shift = c.kp.plane_frame + 2 * L.nm;
     }
+    if (L.wall_bytes) {
+        const size_t nlayer = c.kp.nlayer;
+        c.kp.wsol = (double*)(h->ws + L.wall_off);
+        c.kp.mflu = c.kp.wsol + 2 * 5 * nlayer;
+    }
     c.aux_f = L.aux_bytes ? (float*)(h->ws + L.aux_off) : nullptr;
     c.aux_d = L.aux_bytes ? (double*)(h->ws + L.aux_off) : nullptr;
     c.partials = (double*)(h->ws + L.part_off);
@@ -184,7 +192,7 @@ static holb_status check_flags(holb_sim* s)
     if (e != hipSuccess) return hip_fail(e, "reading the error flags");
     e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    if (flags) return fail(HOLB_ENUMERIC, "device numeric error flags 0x%x (1 density, 2 theta, 4 EOS)", flags);
+    if (flags) return fail(HOLB_ENUMERIC, "device numeric error flags 0x%x (1 density, 2 theta, 4 EOS, 8 wall closure)", flags);
     return HOLB_OK;
 }
 
@@ -199,7 +207,7 @@ holb_status holb_init(holb_sim* s, const float* rho, const float* u, const float
     // buffer and the initial fields as the wall targets of the first step.
     LaunchCtx c = s->ctx(false);
     c.pop_out = s->ws + s->lay.pop_off[s->cur];
-    c.tgt_out = (float*)(s->ws + s->lay.tgt_off[s->cur]);
+    c.tgt_out = (double*)(s->ws + s->lay.tgt_off[s->cur]);
     e = launch_init(c, rho, u, theta ? theta : rho);
     if (e != hipSuccess) return hip_fail(e, "init kernel");
     s->initialized = true;

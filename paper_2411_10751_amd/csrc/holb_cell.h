@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include "holb_device.h"
+#include "holb_wall.h"
 
 namespace holb {
 
@@ -294,25 +295,32 @@ __device__ __forceinline__ void wall_coord(const KParams& p, int x, int y, int z
 // domains and interior planes).
 template <class L, int ST, bool WALLS, int FM, bool MOM1 = false>
 __device__ __forceinline__ void load_state(const KParams& p, const typename Codec<ST>::T* __restrict__ fin,
-                                           const float* __restrict__ tgt_in, int x, int y, int z,
+                                           const double* __restrict__ tgt_in, int x, int y, int z,
                                            float (&f)[L::Q], Frame& fo, float& dr, float (&j)[3], float& ed)
 {
     uint64_t unk = pull_cell<L, ST, WALLS, FM, MOM1>(p, fin, x, y, z, f, fo);
     if (WALLS && p.walls && unk) {
         int kw, nw, cil;
         wall_coord<L>(p, x, y, z, kw, nw, cil);
-        const int slot = wall_slot(kw, nw);
-        float t[5], nb[4] = {0.f, 0.f, 0.f, 0.f};
+        if (kw == 0 || kw == nw - 1) {
+            // wall node: closed at the target solved for this state
+            const int side = kw == 0 ? 0 : 1;
+            WallState T, after;
+            const double* ws = p.wsol + (long long)side * 5 * p.nlayer + cil;
+            T.rho = ws[0];
+            T.u[0] = ws[p.nlayer];
+            T.u[1] = ws[2 * (long long)p.nlayer];
+            T.u[2] = ws[3 * (long long)p.nlayer];
+            T.theta = ws[4 * (long long)p.nlayer];
+            if (side == 0) wall_close<L, 0, true>(p, fo, f, wall_known<L, 0>(fo, f), T, after);
+            else wall_close<L, 1, true>(p, fo, f, wall_known<L, 1>(fo, f), T, after);
+        } else {
+            const int slot = wall_slot(kw, nw);
+            double t[5];
 #pragma unroll
-        for (int c = 0; c < L::D + 2; ++c) t[c] = tgt_in[((long long)slot * (L::D + 2) + c) * p.nlayer + cil];
-        const int wall = kw == 0 ? 0 : (kw == nw - 1 ? 1 : -1);
-        if (wall >= 0) {
-            // the first fluid layer: slot 1 (low wall) or 4 (high wall)
-            const int s1 = wall == 0 ? 1 : 4;
-#pragma unroll
-            for (int c = 1; c < L::D + 2; ++c) nb[c - 1] = tgt_in[((long long)s1 * (L::D + 2) + c) * p.nlayer + cil];
+            for (int c = 0; c < L::D + 2; ++c) t[c] = tgt_in[((long long)slot * (L::D + 2) + c) * p.nlayer + cil];
+            fluid_close<L>(p, fo, f, unk, t);
         }
-        tms_fill<L>(p, fo, f, unk, wall, t, nb);
     }
     moments<L>(f, dr, j, ed);
 }
@@ -401,19 +409,40 @@ __device__ __forceinline__ void grad_theta(const KParams& p, const float* __rest
     }
 }
 
+// The state of a node on the wall layers, kept for the next step's closure
+// (targets of Eq. 4.7).  Density and temperature are stored in FP64 as
+// frame + deviation, without the FP32 rounding of the sum: the closure
+// reflects them about the wall values and is sensitive to their last bits.
 template <class L>
-__device__ __forceinline__ void write_targets(const KParams& p, float* __restrict__ tgt_out, int x, int y, int z,
-                                              const Macro& m)
+__device__ __forceinline__ void write_targets(const KParams& p, double* __restrict__ tgt_out, int x, int y, int z,
+                                              const Frame& fo, const Macro& m)
 {
     int kw, nw, cil;
     wall_coord<L>(p, x, y, z, kw, nw, cil);
     const int slot = wall_slot(kw, nw);
     if (slot < 0) return;
-    float* t = tgt_out + (long long)slot * (L::D + 2) * p.nlayer + cil;
-    t[0] = m.rho;
+    double* t = tgt_out + (long long)slot * (L::D + 2) * p.nlayer + cil;
+    t[0] = (double)fo.rho + (double)m.dr;
 #pragma unroll
     for (int a = 0; a < L::D; ++a) t[(long long)(1 + a) * p.nlayer] = m.u[a];
-    t[(long long)(1 + L::D) * p.nlayer] = m.theta;
+    t[(long long)(1 + L::D) * p.nlayer] = (p.flags & KF_ISO) ? 1.0 : (1.0 + (double)fo.thb) + (double)m.dth;
+}
+
+// A wall node keeps the target it was closed at as the starting point of the
+// next step's solve (warm slot of the targets).
+template <class L>
+__device__ __forceinline__ void write_warm_start(const KParams& p, double* __restrict__ tgt_out, int x, int y, int z)
+{
+    int kw, nw, cil;
+    wall_coord<L>(p, x, y, z, kw, nw, cil);
+    if (kw != 0 && kw != nw - 1) return;
+    const int side = kw == 0 ? 0 : 1;
+    const double* ws = p.wsol + (long long)side * 5 * p.nlayer + cil;
+    double* t = tgt_out + (long long)warm_slot(side) * (L::D + 2) * p.nlayer + cil;
+    t[0] = ws[0];
+#pragma unroll
+    for (int a = 0; a < L::D; ++a) t[(long long)(1 + a) * p.nlayer] = ws[(long long)(1 + a) * p.nlayer];
+    t[(long long)(1 + L::D) * p.nlayer] = ws[4 * (long long)p.nlayer];
 }
 
 template <class L, int ST, int FAM>
@@ -445,8 +474,8 @@ __device__ __forceinline__ float theta_field(const KParams& p, const Frame& fo, 
 template <class L, int ST, int FAM, bool WALLS, int FM>
 __device__ __forceinline__ void step_cell(const KParams& p, const typename Codec<ST>::T* __restrict__ fin,
                                           typename Codec<ST>::T* __restrict__ fout, const float* __restrict__ aux_f,
-                                          const double* __restrict__ aux_d, const float* __restrict__ tgt_in,
-                                          float* __restrict__ tgt_out, int cell)
+                                          const double* __restrict__ aux_d, const double* __restrict__ tgt_in,
+                                          double* __restrict__ tgt_out, int cell)
 {
     using LL = Lat<L>;
     int x, y, z;
@@ -457,7 +486,10 @@ __device__ __forceinline__ void step_cell(const KParams& p, const typename Codec
     Macro m;
     float pc;
     full_macro<L, ST, FAM>(p, fo, aux_f, aux_d, x, y, z, dr, j, ed, m, pc);
-    if (WALLS && p.walls) write_targets<L>(p, tgt_out, x, y, z, m);
+    if (WALLS && p.walls) {
+        write_targets<L>(p, tgt_out, x, y, z, fo, m);
+        write_warm_start<L>(p, tgt_out, x, y, z);
+    }
     float gT[3] = {0.f, 0.f, 0.f};
     float hc = 0.0f;
     if (FAM == FAM_THERMAL) {
@@ -472,7 +504,7 @@ __device__ __forceinline__ void step_cell(const KParams& p, const typename Codec
 // family) of the current state, read by the stencil of the following pass.
 template <class L, int ST, int FAM, bool WALLS, int FM>
 __device__ __forceinline__ void aux_cell(const KParams& p, const typename Codec<ST>::T* __restrict__ fin,
-                                         const float* __restrict__ tgt_in, float* __restrict__ aux_f,
+                                         const double* __restrict__ tgt_in, float* __restrict__ aux_f,
                                          double* __restrict__ aux_d, int cell)
 {
     int x, y, z;
@@ -520,7 +552,7 @@ __device__ __forceinline__ void init_frame_cell(const KParams& p, const float* _
 template <class L, int ST, int FM>
 __device__ __forceinline__ void init_cell(const KParams& p, const float* __restrict__ rho,
                                           const float* __restrict__ u, const float* __restrict__ theta,
-                                          typename Codec<ST>::T* __restrict__ fout, float* __restrict__ tgt, int cell)
+                                          typename Codec<ST>::T* __restrict__ fout, double* __restrict__ tgt, int cell)
 {
     using LL = Lat<L>;
     int x, y, z;
@@ -534,7 +566,22 @@ __device__ __forceinline__ void init_cell(const KParams& p, const float* __restr
     m.thb = m.theta - 1.0f;
     if (!(m.rho > 0.0f) || !(m.rho < 3.0e38f)) raise_err(p, HOLB_ERR_DENSITY_BIT);
     if (!(m.theta > 0.0f) || !(m.theta < 3.0e38f)) raise_err(p, HOLB_ERR_THETA_BIT);
-    if (p.walls) write_targets<L>(p, tgt, x, y, z, m);
+    if (p.walls) {
+        const Frame exact{m.rho, m.thb};  // the initial fields as they are: deviation 0
+        Macro m0 = m;
+        m0.dr = 0.0f;
+        m0.dth = 0.0f;
+        write_targets<L>(p, tgt, x, y, z, exact, m0);
+        int kw, nw, cil;
+        wall_coord<L>(p, x, y, z, kw, nw, cil);
+        if (kw == 0 || kw == nw - 1) {
+            double* t = tgt + (long long)warm_slot(kw == 0 ? 0 : 1) * (L::D + 2) * p.nlayer + cil;
+            t[0] = m.rho;
+#pragma unroll
+            for (int a = 0; a < L::D; ++a) t[(long long)(1 + a) * p.nlayer] = m.u[a];
+            t[(long long)(1 + L::D) * p.nlayer] = m.theta;
+        }
+    }
     const uint32_t* fp = frame_plane<ST>(fout, p.pitch, L::Q);
     const int mz = L::D == 3 ? z : y;
     const Frame fo = FM != FM_PLANE ? unpack_frame(fp[cell]) : plane_frame_of(p, mz);
@@ -557,6 +604,18 @@ __device__ __forceinline__ void init_cell(const KParams& p, const float* __restr
         }
         if (!inside) continue;
         const int slot = (dz * p.ny + dy) * p.nx + dx;
+        if (p.walls) {
+            // A population of this node that would leave through a wall has
+            // a slot no node pulls; it holds the equilibrium the node would
+            // send out, in the node's own frame (before the first step, the
+            // closure balances the mass of these slots).
+            const int mo = (L::D == 2 ? y : z) + cnorm<L>(i), nmo = L::D == 2 ? p.ny : p.nz;
+            if (mo < 0 || mo >= nmo) {
+                float ho = feq_dev<L>(fo, i, m.rho, m.u, m.thb);
+                if constexpr (FM == FM_CELLU) ho -= cdot_mom<L>(i, fp[mom_offset(p.N) + cell]);
+                fout[(long long)i * p.pitch + cell] = Codec<ST>::enc(ho, p.dref[i]);
+            }
+        }
         // in the node's own frame, then moved into the slot cell's frame
         const float fe = feq_dev<L>(fo, i, m.rho, m.u, m.thb);
         float h;

@@ -188,14 +188,12 @@ __device__ __forceinline__ long long mom_offset(int N) { return ((long long)N + 
 // and thb = theta - 1 are the Hermite-scaled invariants of Eq. (2.2) / Table 2.
 
 // Eq. (2.2) for one direction, minus its leading 1: f^eq_i = w_i rho (1 + t).
-template <class L, class R = float>
-__device__ __forceinline__ R feq_t(int i, const float (&uf)[3], float thbf)
+template <class L, class R>
+__device__ __forceinline__ R feq_poly(int i, const R (&u)[3], R thb)
 {
     using LL = Lat<L>;
     constexpr R D = (R)L::D;
     const R ic = (R)(1.0 / L::c0sq);
-    const R u[3] = {(R)uf[0], (R)uf[1], (R)uf[2]};
-    const R thb = (R)thbf;
     const R a = ((R)L::cx[i] * u[0] + (R)L::cy[i] * u[1] + (R)L::cz[i] * u[2]) * ic;
     const R uu = (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) * ic;
     const R xx = (R)LL::c2(i) * ic;
@@ -205,6 +203,13 @@ __device__ __forceinline__ R feq_t(int i, const float (&uf)[3], float thbf)
          + a2 * a2 * ((R)1 / (R)24) - (R)0.25 * a2 * uu + (R)0.125 * uu * uu
          + (R)0.25 * thb * (a2 * (xx - (D + (R)4)) + uu * ((D + (R)2) - xx))
          + (R)0.125 * thb * thb * (xx * xx - (R)2 * (D + (R)2) * xx + D * (D + (R)2));
+}
+
+template <class L, class R = float>
+__device__ __forceinline__ R feq_t(int i, const float (&uf)[3], float thbf)
+{
+    const R u[3] = {(R)uf[0], (R)uf[1], (R)uf[2]};
+    return feq_poly<L, R>(i, u, (R)thbf);
 }
 
 // t0 = t(u = 0, theta0) for a shell of squared speed xx (in c0^2 units).
@@ -343,57 +348,6 @@ __device__ __forceinline__ void macro_from_moments(const KParams& p, const Frame
     if (RAISE) {
         if (!(rho > 0.0f) || !(rho < 3.0e38f)) raise_err(p, HOLB_ERR_DENSITY_BIT);
         if (!(m.theta > 0.0f) || !(m.theta < 3.0e38f)) raise_err(p, HOLB_ERR_THETA_BIT);
-    }
-}
-
-// Section 4.3, Eqs. (4.7)-(4.8): rebuild the populations that streamed in
-// from outside the walls, f_i = f_ibar + f^eq_i(tgt) - f^eq_ibar(loc), where the
-// local state fills the unknown set with the target equilibrium.  The local
-// equilibrium is taken at the opposite index (non-equilibrium bounce-back):
-// a node at the target state then stays there, and a moving wall imposes its
-// velocity.  A wall node targets the reflection 2 u_wall - u_1, 2 theta_wall -
-// theta_1 of the first fluid layer (the wall holds half-way between them).  unk has bit
-// i set for unknown direction i; tgt holds the previous-step (rho, u[D],
-// theta) of this node; wall = 0/1 for a wall node (first/last layer), -1 for
-// a fluid node, whose target is its own previous-step state; nb holds the
-// previous-step (u[D], theta) of the first fluid layer next to a wall node.
-template <class L>
-__device__ __forceinline__ void tms_fill(const KParams& p, const Frame& fr, float (&h)[L::Q], uint64_t unk,
-                                         int wall, const float* tgt, const float* nb)
-{
-    using LL = Lat<L>;
-    constexpr int D = L::D;
-    const float rt = tgt[0];
-    float ut[3] = {0.f, 0.f, 0.f};
-    float tt;
-    if (wall >= 0) {
-#pragma unroll
-        for (int a = 0; a < D; ++a) ut[a] = fmaf(2.0f, p.uwall[wall][a], -nb[a]);
-        tt = fmaf(2.0f, p.twall[wall], -nb[D]);
-    } else {
-#pragma unroll
-        for (int a = 0; a < D; ++a) ut[a] = tgt[1 + a];
-        tt = tgt[1 + D];
-    }
-    if (p.flags & KF_ISO) tt = 1.0f;
-    const float tbt = tt - 1.0f;
-#pragma unroll
-    for (int i = 0; i < L::Q; ++i)
-        if ((unk >> i) & 1ull) h[i] = feq_dev<L>(fr, i, rt, ut, tbt);  // target equilibrium, for now
-    float drl, jl[3], edl;
-    moments<L>(h, drl, jl, edl);
-    const float zero3[3] = {0.f, 0.f, 0.f};
-    Macro loc;
-    macro_from_moments<L, false>(p, fr, drl, jl, edl, zero3, loc);
-    // the difference of the two equilibria is small next to each of them:
-    // form it in FP64 (wall layers only)
-#pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-        if ((unk >> i) & 1ull) {
-            const double et = (double)rt * (1.0 + feq_t<L, double>(i, ut, tbt));
-            const double el = (double)loc.rho * (1.0 + feq_t<L, double>(LL::opp(i), loc.u, loc.thb));
-            h[i] = h[LL::opp(i)] + (float)(et - el);
-        }
     }
 }
 

@@ -20,8 +20,8 @@ struct LaunchCtx {
     void* pop_out;        // next state
     float* aux_f;         // theta field (thermal split path)
     double* aux_d;        // psi field (pressure-tensor path)
-    const float* tgt_in;  // wall targets read this step
-    float* tgt_out;       // wall targets written this step
+    const double* tgt_in;  // wall targets read this step
+    double* tgt_out;       // wall targets written this step
     double* partials;     // reduction partials
     int max_partials;     // capacity in blocks
     hipStream_t stream;

@@ -2,10 +2,12 @@
 // (templates; instantiated per lattice and storage set by holb_inst_*.hip).
 //
 // Data layout: populations are structure-of-arrays, Q planes of `pitch`
-// elements (256-byte aligned), cell = x + nx * (y + ny * z).  16-bit storage
-// keeps a frame per cell (binary16 pair rho, theta - 1) in a plane after the
-// populations; FP32 storage uses fixed per-plane frames held in a small table
-// (FrameMode in holb_params.h).  The state buffer
+// elements (256-byte aligned), cell = x + nx * (y + ny * z).  The stored
+// values are deviations from a frame (FrameMode in holb_params.h): per cell
+// (binary16 pair rho, theta - 1 in a plane after the populations, with the
+// momentum in a second plane for FM_CELLU) or fixed per plane along the last
+// axis (a small table); the frame mode is chosen per configuration, for any
+// storage width (holb_host.h).  The state buffer
 // holds the post-collision populations of the last step; a step pulls
 // f^_i(x) = buf[i][x - c_i] (streaming, left side of Eq. 4.4), applies the wall
 // closure, forms the shifted moments (Eq. 4.5), the sources and the collision,
@@ -42,7 +44,7 @@ k_init_frame(const KParams p, const float* __restrict__ rho, const float* __rest
 template <class L, int ST, int FM>
 __global__ void __launch_bounds__(GEN_BLOCK)
 k_init(const KParams p, const float* __restrict__ rho, const float* __restrict__ u,
-       const float* __restrict__ theta, typename Codec<ST>::T* __restrict__ fout, float* __restrict__ tgt)
+       const float* __restrict__ theta, typename Codec<ST>::T* __restrict__ fout, double* __restrict__ tgt)
 {
     const int cell = xcd_block() * GEN_BLOCK + threadIdx.x;
     if (cell < p.N) init_cell<L, ST, FM>(p, rho, u, theta, fout, tgt, cell);
@@ -116,10 +118,116 @@ __device__ __forceinline__ int plane_cell(const KParams& p, const PlaneSet& ps, 
     return plane * p.nlayer + r;
 }
 
+// Wall closure, first half: the mass that the closure of the two fluid
+// boundary layers next to each wall rebuilds (FP64), per column.
+template <class L, int ST, int FM>
+__global__ void __launch_bounds__(GEN_BLOCK)
+k_wall_fluid(const KParams p, const typename Codec<ST>::T* __restrict__ fin, const double* __restrict__ tgt_in)
+{
+    const int c = blockIdx.x * GEN_BLOCK + threadIdx.x;
+    if (c >= 4 * p.nlayer) return;
+    const int q = (int)fastdiv((unsigned)c, p.div_layer), cil = c - q * p.nlayer;
+    const int side = q >> 1, d = 1 + (q & 1);
+    const int nm = L::D == 3 ? p.nz : p.ny;
+    const int k = side == 0 ? d : nm - 1 - d;
+    int x, y, z;
+    cell_coords<L>(p, k * p.nlayer + cil, x, y, z);
+    float f[L::Q];
+    Frame fo;
+    const uint64_t unk = pull_cell<L, ST, true, FM, true>(p, fin, x, y, z, f, fo);
+    double t[5];
+#pragma unroll
+    for (int cc = 0; cc < L::D + 2; ++cc) t[cc] = tgt_in[((long long)wall_slot(k, nm) * (L::D + 2) + cc) * p.nlayer + cil];
+    p.mflu[(long long)q * p.nlayer + cil] = fluid_close<L>(p, fo, f, unk, t);
+}
+
+// Absolute value (FP64) of the stored population j at cell, in the frame it
+// was stored in.
+template <class L, int ST, int FM>
+__device__ __forceinline__ double stored_population(const KParams& p, const typename Codec<ST>::T* __restrict__ fin,
+                                                    int j, int cell, int plane)
+{
+    double v = (double)Codec<ST>::dec(fin[(long long)j * p.pitch + cell], p.dref[j]);
+    Frame F;
+    if constexpr (FM == FM_PLANE) {
+        F = plane_frame_of(p, plane);
+    } else {
+        const uint32_t* fp = frame_plane<ST>(fin, p.pitch, L::Q);
+        F = unpack_frame(fp[cell]);
+        if constexpr (FM == FM_CELLU) v += (double)cdot_mom<L>(j, fp[mom_offset(p.N) + cell]);
+    }
+    return L::shell_w[L::shell[j]] * (v + (double)F.rho * rest_bracket64<L>(L::shell[j], (double)F.thb));
+}
+
+// Wall closure, second half: the target of each wall node (see holb_wall.h).
+template <class L, int ST, int FM, int SIDE>
+__device__ __forceinline__ void wall_solve_cell(const KParams& p, const typename Codec<ST>::T* __restrict__ fin,
+                                                const double* __restrict__ tgt_in, int cil)
+{
+    constexpr int D = L::D;
+    const int nm = D == 3 ? p.nz : p.ny;
+    const int k0 = SIDE == 0 ? 0 : nm - 1;
+    int x, y, z;
+    cell_coords<L>(p, k0 * p.nlayer + cil, x, y, z);
+    float f[L::Q];
+    Frame fo;
+    pull_cell<L, ST, true, FM, true>(p, fin, x, y, z, f, fo);
+    const WallKnown K = wall_known<L, SIDE>(fo, f);
+    // the mass that left through this wall in the last streaming: the
+    // populations of the column's first three nodes that point out of the
+    // domain (their slots are pulled by no node)
+    double out = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int k = SIDE == 0 ? d : nm - 1 - d;
+        const int cell = k * p.nlayer + cil;
+#pragma unroll
+        for (int j = 0; j < L::Q; ++j)
+            if (SIDE == 0 ? cnorm<L>(j) < -d : cnorm<L>(j) > d) out += stored_population<L, ST, FM>(p, fin, j, cell, k);
+    }
+    const double want = out - p.mflu[(long long)(2 * SIDE) * p.nlayer + cil] -
+                        p.mflu[(long long)(2 * SIDE + 1) * p.nlayer + cil];
+    // the reflection of the first fluid node's previous-step fields
+    const int s1 = wall_slot(SIDE == 0 ? 1 : nm - 2, nm);
+    const double* t1 = tgt_in + (long long)s1 * (D + 2) * p.nlayer + cil;
+    double udes[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < D; ++a) udes[a] = 2.0 * (double)p.uwall[SIDE][a] - t1[(long long)(1 + a) * p.nlayer];
+    const bool iso = p.flags & KF_ISO;
+    const double thdes = iso ? 1.0 : 2.0 * (double)p.twall[SIDE] - t1[(long long)(1 + D) * p.nlayer];
+    // start from the target of the previous step
+    const double* tw = tgt_in + (long long)warm_slot(SIDE) * (D + 2) * p.nlayer + cil;
+    WallState T;
+    T.rho = tw[0];
+    T.u[0] = T.u[1] = T.u[2] = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) T.u[a] = tw[(long long)(1 + a) * p.nlayer];
+    T.theta = tw[(long long)(1 + D) * p.nlayer];
+    const bool ok = iso ? wall_solve<L, SIDE, D>(p, fo, f, K, want, udes, thdes, T)
+                        : wall_solve<L, SIDE, D + 1>(p, fo, f, K, want, udes, thdes, T);
+    if (!ok) raise_err(p, HOLB_ERR_WALL_BIT);
+    double* ws = p.wsol + (long long)SIDE * 5 * p.nlayer + cil;
+    ws[0] = T.rho;
+    ws[p.nlayer] = T.u[0];
+    ws[2 * (long long)p.nlayer] = T.u[1];
+    ws[3 * (long long)p.nlayer] = T.u[2];
+    ws[4 * (long long)p.nlayer] = T.theta;
+}
+
+template <class L, int ST, int FM>
+__global__ void __launch_bounds__(64)
+k_wall_solve(const KParams p, const typename Codec<ST>::T* __restrict__ fin, const double* __restrict__ tgt_in)
+{
+    const int cil = blockIdx.x * 64 + threadIdx.x;
+    if (cil >= p.nlayer) return;
+    if (blockIdx.y == 0) wall_solve_cell<L, ST, FM, 0>(p, fin, tgt_in, cil);
+    else wall_solve_cell<L, ST, FM, 1>(p, fin, tgt_in, cil);
+}
+
 template <class L, int ST, int FAM, bool WALLS, int FM>
 __global__ void __launch_bounds__(GEN_BLOCK)
 k_aux(const KParams p, const PlaneSet ps, const typename Codec<ST>::T* __restrict__ fin,
-      const float* __restrict__ tgt_in, float* __restrict__ aux_f, double* __restrict__ aux_d, int remap)
+      const double* __restrict__ tgt_in, float* __restrict__ aux_f, double* __restrict__ aux_d, int remap)
 {
     const int c = xcd_block(remap) * GEN_BLOCK + threadIdx.x;
     if (c < (ps.n0 + ps.n1) * p.nlayer)
@@ -130,7 +238,7 @@ template <class L, int ST, int FAM, bool WALLS, int FM>
 __global__ void __launch_bounds__(GEN_BLOCK)
 k_step(const KParams p, const PlaneSet ps, const typename Codec<ST>::T* __restrict__ fin,
        typename Codec<ST>::T* __restrict__ fout, const float* __restrict__ aux_f, const double* __restrict__ aux_d,
-       const float* __restrict__ tgt_in, float* __restrict__ tgt_out, int remap)
+       const double* __restrict__ tgt_in, double* __restrict__ tgt_out, int remap)
 {
     const int c = xcd_block(remap) * GEN_BLOCK + threadIdx.x;
     if (c < (ps.n0 + ps.n1) * p.nlayer)
@@ -141,7 +249,7 @@ k_step(const KParams p, const PlaneSet ps, const typename Codec<ST>::T* __restri
 template <class L, int ST, int FAM, bool WALLS, int FM>
 __global__ void __launch_bounds__(GEN_BLOCK)
 k_fields(const KParams p, const typename Codec<ST>::T* __restrict__ fin, const float* __restrict__ aux_f,
-         const double* __restrict__ aux_d, const float* __restrict__ tgt_in, float* __restrict__ rho_out,
+         const double* __restrict__ aux_d, const double* __restrict__ tgt_in, float* __restrict__ rho_out,
          float* __restrict__ u_out, float* __restrict__ th_out)
 {
     const int cell = xcd_block() * GEN_BLOCK + threadIdx.x;
@@ -174,7 +282,7 @@ __device__ __forceinline__ double wave_sum(double v)
 template <class L, int ST, int FAM, bool WALLS, int FM>
 __global__ void __launch_bounds__(GEN_BLOCK)
 k_reduce(const KParams p, const typename Codec<ST>::T* __restrict__ fin, const float* __restrict__ aux_f,
-         const double* __restrict__ aux_d, const float* __restrict__ tgt_in, double* __restrict__ partials)
+         const double* __restrict__ aux_d, const double* __restrict__ tgt_in, double* __restrict__ partials)
 {
     __shared__ double red[GEN_BLOCK / 64][5];
     const int cell = blockIdx.x * GEN_BLOCK + threadIdx.x;
@@ -273,7 +381,21 @@ struct Launch {
         hipError_t r = hipGetLastError();
         if (r != hipSuccess) return r;
         hipLaunchKernelGGL((k_init<L, ST, FM>), dim3(nblocks_for(c.kp.N)), dim3(GEN_BLOCK), 0, c.stream, c.kp, rho, u,
-                           th, (T*)c.pop_out, (float*)c.tgt_out);
+                           th, (T*)c.pop_out, c.tgt_out);
+        return hipGetLastError();
+    }
+
+    // Walled domains: solve the wall-node targets of the current state
+    // (before any pass that closes the wall layers).
+    static hipError_t wall_prep(const LaunchCtx& c)
+    {
+        if (!c.kp.walls) return hipSuccess;
+        hipLaunchKernelGGL((k_wall_fluid<L, ST, FM>), dim3(nblocks_for(4 * c.kp.nlayer)), dim3(GEN_BLOCK), 0,
+                           c.stream, c.kp, (const T*)c.pop_in, c.tgt_in);
+        hipError_t r = hipGetLastError();
+        if (r != hipSuccess) return r;
+        hipLaunchKernelGGL((k_wall_solve<L, ST, FM>), dim3((c.kp.nlayer + 63) / 64, 2), dim3(64), 0, c.stream, c.kp,
+                           (const T*)c.pop_in, c.tgt_in);
         return hipGetLastError();
     }
 
@@ -336,7 +458,8 @@ struct Launch {
 
     static hipError_t step(const LaunchCtx& c)
     {
-        hipError_t r = aux(c);
+        hipError_t r = wall_prep(c);
+        if (r == hipSuccess) r = aux(c);
         if (r != hipSuccess) return r;
         if (!c.kp.walls) return timed(c, [&] { return step_planes(c, all(c.kp), false); });
         r = step_planes(c, wall_layers(c.kp), true);
@@ -355,6 +478,8 @@ struct Launch {
 
     static hipError_t fields(const LaunchCtx& c, float* rho, float* u, float* th)
     {
+        hipError_t rp = wall_prep(c);
+        if (rp != hipSuccess) return rp;
         if (FAM == FAM_PTENSOR) {
             hipError_t r = aux(c);
             if (r != hipSuccess) return r;
@@ -370,6 +495,8 @@ struct Launch {
 
     static hipError_t reduce(const LaunchCtx& c, double* out)
     {
+        hipError_t rp = wall_prep(c);
+        if (rp != hipSuccess) return rp;
         if (FAM == FAM_PTENSOR) {
             hipError_t r = aux(c);
             if (r != hipSuccess) return r;
@@ -397,7 +524,10 @@ inline hipError_t dispatch_family(const LaunchCtx& c, int op, const float* a, co
     switch (op) {                                                      \
     case 0: return Launch<L, ST, FAM, FM>::init(c, a, b, d);           \
     case 1: return Launch<L, ST, FAM, FM>::step(c);                    \
-    case 2: return Launch<L, ST, FAM, FM>::aux(c);                     \
+    case 2: {                                                          \
+        hipError_t r = Launch<L, ST, FAM, FM>::wall_prep(c);           \
+        return r == hipSuccess ? Launch<L, ST, FAM, FM>::aux(c) : r;   \
+    }                                                                  \
     case 3: return Launch<L, ST, FAM, FM>::fields(c, o1, o2, o3);      \
     case 4: return Launch<L, ST, FAM, FM>::reduce(c, dout);            \
     }

@@ -19,7 +19,7 @@ enum : unsigned { KF_BODY = 1u, KF_ISO = 2u };
 // along the last axis, kept in a small table.
 enum FrameMode { FM_CELL = 0, FM_PLANE = 1, FM_CELLU = 2 };
 
-enum : unsigned { HOLB_ERR_DENSITY_BIT = 1u, HOLB_ERR_THETA_BIT = 2u, HOLB_ERR_EOS_BIT = 4u };
+enum : unsigned { HOLB_ERR_DENSITY_BIT = 1u, HOLB_ERR_THETA_BIT = 2u, HOLB_ERR_EOS_BIT = 4u, HOLB_ERR_WALL_BIT = 8u };
 // equation of state of the pseudopotential (values of HOLB_EOS_*)
 enum : int { EOS_VDW = 0, EOS_CS = 1 };
 
@@ -75,13 +75,24 @@ struct KParams {
     // [(m * 7 + c_m + 3) * NS + s] for plane m, last-axis velocity component c_m, shell s
     const float* plane_frame;
     const float* plane_shift;
+    // Walled domains: the wall-node targets solved for the current state
+    // (FP64, [side][component rho, u[3], theta][cell in layer]), and the mass
+    // rebuilt by the closure of the two fluid boundary layers of each wall
+    // ([side][distance 1, 2 from the wall][cell in layer]).
+    double* wsol;
+    double* mflu;
 };
 
-// Wall targets: 6 layers (3 per wall) x nlayer cells x (D + 2) floats, laid
-// out [layer slot][component][cell in layer].
+// Wall targets: 8 slots x (D + 2) components x nlayer cells, doubles, laid out
+// [slot][component][cell in layer].  Slots 0-5 hold the previous-step rho,
+// u[D], theta of the 6 boundary layers (3 per wall, wall_slot); slots 6 and
+// 7 the wall-node target solved in the previous step at the low and high
+// wall (the starting point of the next solve).
+constexpr int TGT_SLOTS = 8;
 __host__ __device__ inline int wall_slot(int k, int n)
 {
     return k < 3 ? k : (k >= n - 3 ? k - (n - 6) : -1);
 }
+__host__ __device__ inline int warm_slot(int side) { return 6 + side; }
 
 }  // namespace holb

@@ -178,6 +178,18 @@ holb_status holb_fields(holb_sim* s, float* rho, float* u, float* theta);
  * returns HOLB_ENUMERIC if the device error flags are set. */
 holb_status holb_reduce(holb_sim* s, double out[5]);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): holb_reduce
+ * with its FP64 block partials and totals kept in a library-owned static
+ * device array (about 5 MB per GPU, held until the process ends) instead of
+ * the workspace.  Same kernels and partition, so the totals are bitwise those
+ * of holb_reduce.  Grids of more than HOLB_NOALLOC_MAX_CELLS cells are
+ * rejected with HOLB_ESIZE.  All calls on one GPU share the array: calls that
+ * overlap on one GPU (other threads, other streams) race.  Allocates nothing;
+ * synchronises; HOLB_ENUMERIC if the device error flags are set. */
+#define HOLB_NOALLOC_MAX_CELLS 33554432
+holb_status holb_reduce_noalloc(holb_sim* s, double out[5]);
+
 /* Device error flags (HOLB_ERR_*) raised since creation; synchronises. */
 holb_status holb_error_flags(holb_sim* s, uint32_t* flags);
 

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -249,6 +250,58 @@ holb_status holb_reduce(holb_sim* s, double out[5])
     if (!s->initialized) return fail(HOLB_ESTATE, "holb_reduce before holb_init");
     double* dout = (double*)(s->ws + s->lay.out_off);
     hipError_t e = launch_reduce(s->ctx(false), dout);
+    if (e != hipSuccess) return hip_fail(e, "reduce kernel");
+    e = hipMemcpyAsync(out, dout, 5 * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "copying the totals");
+    return check_flags(s);
+}
+
+// holb_reduce_noalloc: the block partials (5 doubles per 256-cell block) and
+// the 5 totals in a file-scope device array.  Host code never uses the
+// array's name as an address: its device address is looked up once per
+// device (hipGetSymbolAddress) and kept.
+namespace {
+constexpr int NOALLOC_BLOCKS = HOLB_NOALLOC_MAX_CELLS / 256;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[NOALLOC_MAX_DEVICES] = {};
+}  // namespace
+
+static __device__ __align__(256) double scratch[(size_t)NOALLOC_BLOCKS * 5 + 8];
+
+static holb_status scratch_of_current_device(double** out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(HOLB_EUNSUPPORTED, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress of the static scratch array");
+        g_scratch_dev[dev] = (double*)ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return HOLB_OK;
+}
+
+holb_status holb_reduce_noalloc(holb_sim* s, double out[5])
+{
+    if (!s || !out) return fail(HOLB_EINVAL, "NULL argument");
+    const int nb = reduce_blocks(s->base);
+    if (nb > NOALLOC_BLOCKS)
+        return fail(HOLB_ESIZE, "holb_reduce_noalloc takes at most %d cells, the grid has %d", HOLB_NOALLOC_MAX_CELLS,
+                    s->base.kp.N);
+    if (!s->initialized) return fail(HOLB_ESTATE, "holb_reduce_noalloc before holb_init");
+    double* sp = nullptr;
+    holb_status st = scratch_of_current_device(&sp);
+    if (st) return st;
+    LaunchCtx c = s->ctx(false);
+    c.partials = sp;
+    c.max_partials = NOALLOC_BLOCKS;
+    double* dout = sp + (size_t)NOALLOC_BLOCKS * 5;
+    hipError_t e = launch_reduce(c, dout);
     if (e != hipSuccess) return hip_fail(e, "reduce kernel");
     e = hipMemcpyAsync(out, dout, 5 * sizeof(double), hipMemcpyDeviceToHost, s->stream);
     if (e != hipSuccess) return hip_fail(e, "copying the totals");

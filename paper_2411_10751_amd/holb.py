@@ -80,6 +80,7 @@ _sig = {
     "holb_step": ([_vp, ctypes.c_int64], ctypes.c_int32),
     "holb_fields": ([_vp, _vp, _vp, _vp], ctypes.c_int32),
     "holb_reduce": ([_vp, _P(ctypes.c_double)], ctypes.c_int32),
+    "holb_reduce_noalloc": ([_vp, _P(ctypes.c_double)], ctypes.c_int32),
     "holb_error_flags": ([_vp, _P(ctypes.c_uint32)], ctypes.c_int32),
     "holb_state_bytes": ([_vp, _P(ctypes.c_size_t)], ctypes.c_int32),
     "holb_get_state": ([_vp, _vp, ctypes.c_size_t], ctypes.c_int32),
@@ -247,6 +248,11 @@ class Sim:
     def reduce(self):
         out = (ctypes.c_double * 5)()
         check(holb_reduce(self._h, out), "holb_reduce")
+        return np.array(out[:])
+
+    def reduce_noalloc(self):
+        out = (ctypes.c_double * 5)()
+        check(holb_reduce_noalloc(self._h, out), "holb_reduce_noalloc")
         return np.array(out[:])
 
     def error_flags(self):

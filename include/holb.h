@@ -209,9 +209,11 @@ holb_status holb_error_flags(holb_sim* s, uint32_t* flags);
  * With walls, the wall targets follow (again 256-byte aligned): for the
  * three layers next to each wall (layer k = 0, 1, 2 from the low wall, then
  * n-3, n-2, n-1), the last step's rho, u[D] and theta, each a plane of the
- * layer's cells (float); then, for the low and the high wall, the wall-node
+ * layer's cells (double); then, for the low and the high wall, the wall-node
  * target the last step solved (rho, u[D], theta, planes of the layer's cells:
- * the starting point of the next solve).  Restoring them makes a resumed
+ * the starting point of the next solve); then, per wall, the 16 LU factors of
+ * the Jacobian that solve used (4 x 4 row-major, each a plane of the layer's
+ * cells; all zero before the first step).  Restoring them makes a resumed
  * walled run continue bitwise as the uninterrupted one.  Slots of the first
  * three layers whose population would leave through a wall are pulled by no
  * node: they hold the outflow whose mass the next closure gives back.  holb_set_state needs no

@@ -68,8 +68,8 @@ Layout layout_of(const holb_config* c)
     L.aux_off = off; off = align_up(off + L.aux_bytes);
     if (c->walls) {
         const size_t nlayer = D == 2 ? (size_t)c->nx : (size_t)c->nx * c->ny;
-        L.tgt_bytes = TGT_SLOTS * (size_t)(D + 2) * nlayer * sizeof(double);
-        L.wall_bytes = (2 * 5 + 2 * 2) * nlayer * sizeof(double);
+        L.tgt_bytes = (TGT_SLOTS * (size_t)(D + 2) + 2 * 16) * nlayer * sizeof(double);
+        L.wall_bytes = (2 * WSOL_COMPS + 2 * 2) * nlayer * sizeof(double) + 2 * WCLOSED_SLOTS * nlayer * sizeof(float);
     }
     L.tgt_off[0] = off; off = align_up(off + L.tgt_bytes);
     L.tgt_off[1] = off; off = align_up(off + L.tgt_bytes);
@@ -175,7 +175,8 @@ holb_status holb_create(const holb_config* cfg, void* dev_workspace, size_t byte
     if (L.wall_bytes) {
         const size_t nlayer = c.kp.nlayer;
         c.kp.wsol = (double*)(h->ws + L.wall_off);
-        c.kp.mflu = c.kp.wsol + 2 * 5 * nlayer;
+        c.kp.mflu = c.kp.wsol + 2 * WSOL_COMPS * nlayer;
+        c.kp.wclosed = (float*)(c.kp.mflu + 2 * 2 * nlayer);
     }
     c.aux_f = L.aux_bytes ? (float*)(h->ws + L.aux_off) : nullptr;
     c.aux_d = L.aux_bytes ? (double*)(h->ws + L.aux_off) : nullptr;

@@ -300,27 +300,12 @@ __device__ __forceinline__ void load_state(const KParams& p, const typename Code
 {
     uint64_t unk = pull_cell<L, ST, WALLS, FM, MOM1>(p, fin, x, y, z, f, fo);
     if (WALLS && p.walls && unk) {
+        // the closure of this state, solved before any pass (k_wall_fluid,
+        // k_wall_solve): read its populations
         int kw, nw, cil;
         wall_coord<L>(p, x, y, z, kw, nw, cil);
-        if (kw == 0 || kw == nw - 1) {
-            // wall node: closed at the target solved for this state
-            const int side = kw == 0 ? 0 : 1;
-            WallState T, after;
-            const double* ws = p.wsol + (long long)side * 5 * p.nlayer + cil;
-            T.rho = ws[0];
-            T.u[0] = ws[p.nlayer];
-            T.u[1] = ws[2 * (long long)p.nlayer];
-            T.u[2] = ws[3 * (long long)p.nlayer];
-            T.theta = ws[4 * (long long)p.nlayer];
-            if (side == 0) wall_close<L, 0, true>(p, fo, f, wall_known<L, 0>(fo, f), T, after);
-            else wall_close<L, 1, true>(p, fo, f, wall_known<L, 1>(fo, f), T, after);
-        } else {
-            const int slot = wall_slot(kw, nw);
-            double t[5];
-#pragma unroll
-            for (int c = 0; c < L::D + 2; ++c) t[c] = tgt_in[((long long)slot * (L::D + 2) + c) * p.nlayer + cil];
-            fluid_close<L>(p, fo, f, unk, t);
-        }
+        if (kw < 3) load_closed<L, 0>(p, kw, cil, f);
+        else load_closed<L, 1>(p, nw - 1 - kw, cil, f);
     }
     moments<L>(f, dr, j, ed);
 }
@@ -437,12 +422,15 @@ __device__ __forceinline__ void write_warm_start(const KParams& p, double* __res
     wall_coord<L>(p, x, y, z, kw, nw, cil);
     if (kw != 0 && kw != nw - 1) return;
     const int side = kw == 0 ? 0 : 1;
-    const double* ws = p.wsol + (long long)side * 5 * p.nlayer + cil;
+    const double* ws = p.wsol + (long long)side * WSOL_COMPS * p.nlayer + cil;
     double* t = tgt_out + (long long)warm_slot(side) * (L::D + 2) * p.nlayer + cil;
     t[0] = ws[0];
 #pragma unroll
     for (int a = 0; a < L::D; ++a) t[(long long)(1 + a) * p.nlayer] = ws[(long long)(1 + a) * p.nlayer];
     t[(long long)(1 + L::D) * p.nlayer] = ws[4 * (long long)p.nlayer];
+    double* lu = tgt_out + tgt_lu_offset(L::D, side, p.nlayer) + cil;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) lu[(long long)k * p.nlayer] = ws[(long long)(5 + k) * p.nlayer];
 }
 
 template <class L, int ST, int FAM>
@@ -580,6 +568,9 @@ __device__ __forceinline__ void init_cell(const KParams& p, const float* __restr
 #pragma unroll
             for (int a = 0; a < L::D; ++a) t[(long long)(1 + a) * p.nlayer] = m.u[a];
             t[(long long)(1 + L::D) * p.nlayer] = m.theta;
+            double* lu = tgt + tgt_lu_offset(L::D, kw == 0 ? 0 : 1, p.nlayer) + cil;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) lu[(long long)k * p.nlayer] = 0.0;  // no Jacobian yet
         }
     }
     const uint32_t* fp = frame_plane<ST>(fout, p.pitch, L::Q);

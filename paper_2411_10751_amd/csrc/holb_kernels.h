@@ -122,7 +122,8 @@ __device__ __forceinline__ int plane_cell(const KParams& p, const PlaneSet& ps, 
 // boundary layers next to each wall rebuilds (FP64), per column.
 template <class L, int ST, int FM>
 __global__ void __launch_bounds__(GEN_BLOCK)
-k_wall_fluid(const KParams p, const typename Codec<ST>::T* __restrict__ fin, const double* __restrict__ tgt_in)
+k_wall_fluid(const KParams p, const typename Codec<ST>::T* __restrict__ fin, const double* __restrict__ tgt_in,
+             float* __restrict__ theta_out)
 {
     const int c = blockIdx.x * GEN_BLOCK + threadIdx.x;
     if (c >= 4 * p.nlayer) return;
@@ -134,11 +135,16 @@ k_wall_fluid(const KParams p, const typename Codec<ST>::T* __restrict__ fin, con
     cell_coords<L>(p, k * p.nlayer + cil, x, y, z);
     float f[L::Q];
     Frame fo;
-    const uint64_t unk = pull_cell<L, ST, true, FM, true>(p, fin, x, y, z, f, fo);
+    pull_cell<L, ST, true, FM, true>(p, fin, x, y, z, f, fo);
     double t[5];
 #pragma unroll
     for (int cc = 0; cc < L::D + 2; ++cc) t[cc] = tgt_in[((long long)wall_slot(k, nm) * (L::D + 2) + cc) * p.nlayer + cil];
-    p.mflu[(long long)q * p.nlayer + cil] = fluid_close<L>(p, fo, f, unk, t);
+    WallState after;
+    p.mflu[(long long)q * p.nlayer + cil] = fluid_close<L>(p, fo, f, t, k, nm, after);
+    if (side == 0) store_closed<L, 0>(p, d, cil, f);
+    else store_closed<L, 1>(p, d, cil, f);
+    // the temperature field of the gradient stencil on the wall layers
+    if (theta_out) theta_out[k * p.nlayer + cil] = theta_field64(p, after);
 }
 
 // Absolute value (FP64) of the stored population j at cell, in the frame it
@@ -162,7 +168,8 @@ __device__ __forceinline__ double stored_population(const KParams& p, const type
 // Wall closure, second half: the target of each wall node (see holb_wall.h).
 template <class L, int ST, int FM, int SIDE>
 __device__ __forceinline__ void wall_solve_cell(const KParams& p, const typename Codec<ST>::T* __restrict__ fin,
-                                                const double* __restrict__ tgt_in, int cil)
+                                                const double* __restrict__ tgt_in, float* __restrict__ theta_out,
+                                                int cil)
 {
     constexpr int D = L::D;
     const int nm = D == 3 ? p.nz : p.ny;
@@ -203,25 +210,39 @@ __device__ __forceinline__ void wall_solve_cell(const KParams& p, const typename
 #pragma unroll
     for (int a = 0; a < D; ++a) T.u[a] = tw[(long long)(1 + a) * p.nlayer];
     T.theta = tw[(long long)(1 + D) * p.nlayer];
-    const bool ok = iso ? wall_solve<L, SIDE, D>(p, fo, f, K, want, udes, thdes, T)
-                        : wall_solve<L, SIDE, D + 1>(p, fo, f, K, want, udes, thdes, T);
+    // and with the Jacobian factors of the previous step, if there are any
+    double LU[4][4];
+    const double* lu = tgt_in + tgt_lu_offset(D, SIDE, p.nlayer) + cil;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) LU[k / 4][k % 4] = lu[(long long)k * p.nlayer];
+    const bool have = LU[0][0] != 0.0;
+    const bool ok = iso ? wall_solve<L, SIDE, D>(p, fo, f, K, want, udes, thdes, T, LU, have)
+                        : wall_solve<L, SIDE, D + 1>(p, fo, f, K, want, udes, thdes, T, LU, have);
     if (!ok) raise_err(p, HOLB_ERR_WALL_BIT);
-    double* ws = p.wsol + (long long)SIDE * 5 * p.nlayer + cil;
+    double* ws = p.wsol + (long long)SIDE * WSOL_COMPS * p.nlayer + cil;
     ws[0] = T.rho;
     ws[p.nlayer] = T.u[0];
     ws[2 * (long long)p.nlayer] = T.u[1];
     ws[3 * (long long)p.nlayer] = T.u[2];
     ws[4 * (long long)p.nlayer] = T.theta;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) ws[(long long)(5 + k) * p.nlayer] = LU[k / 4][k % 4];
+    // the wall node closed at the solved target, for every pass
+    WallState after;
+    wall_close<L, SIDE, true>(p, fo, f, K, T, after);
+    store_closed<L, SIDE>(p, 0, cil, f);
+    if (theta_out) theta_out[k0 * p.nlayer + cil] = theta_field64(p, after);
 }
 
 template <class L, int ST, int FM>
 __global__ void __launch_bounds__(64)
-k_wall_solve(const KParams p, const typename Codec<ST>::T* __restrict__ fin, const double* __restrict__ tgt_in)
+k_wall_solve(const KParams p, const typename Codec<ST>::T* __restrict__ fin, const double* __restrict__ tgt_in,
+             float* __restrict__ theta_out)
 {
     const int cil = blockIdx.x * 64 + threadIdx.x;
     if (cil >= p.nlayer) return;
-    if (blockIdx.y == 0) wall_solve_cell<L, ST, FM, 0>(p, fin, tgt_in, cil);
-    else wall_solve_cell<L, ST, FM, 1>(p, fin, tgt_in, cil);
+    if (blockIdx.y == 0) wall_solve_cell<L, ST, FM, 0>(p, fin, tgt_in, theta_out, cil);
+    else wall_solve_cell<L, ST, FM, 1>(p, fin, tgt_in, theta_out, cil);
 }
 
 template <class L, int ST, int FAM, bool WALLS, int FM>
@@ -386,16 +407,19 @@ struct Launch {
     }
 
     // Walled domains: solve the wall-node targets of the current state
-    // (before any pass that closes the wall layers).
+    // (before any pass that closes the wall layers).  With the thermal
+    // source the same two kernels also write the temperature field of the
+    // wall layers, which the field pass then skips.
     static hipError_t wall_prep(const LaunchCtx& c)
     {
         if (!c.kp.walls) return hipSuccess;
+        float* th = FAM == FAM_THERMAL ? c.aux_f : nullptr;
         hipLaunchKernelGGL((k_wall_fluid<L, ST, FM>), dim3(nblocks_for(4 * c.kp.nlayer)), dim3(GEN_BLOCK), 0,
-                           c.stream, c.kp, (const T*)c.pop_in, c.tgt_in);
+                           c.stream, c.kp, (const T*)c.pop_in, c.tgt_in, th);
         hipError_t r = hipGetLastError();
         if (r != hipSuccess) return r;
         hipLaunchKernelGGL((k_wall_solve<L, ST, FM>), dim3((c.kp.nlayer + 63) / 64, 2), dim3(64), 0, c.stream, c.kp,
-                           (const T*)c.pop_in, c.tgt_in);
+                           (const T*)c.pop_in, c.tgt_in, th);
         return hipGetLastError();
     }
 
@@ -433,12 +457,12 @@ struct Launch {
     static PlaneSet wall_layers(const KParams& p) { return PlaneSet{0, 3, nm(p) - 3, 3}; }
     static PlaneSet inner_planes(const KParams& p) { return PlaneSet{3, nm(p) - 6, 0, 0}; }
 
+    // Field pass of the current state; with walls, the interior planes only
+    // (wall_prep, which always runs first, has written the wall layers).
     static hipError_t aux(const LaunchCtx& c)
     {
         if (!c.kp.walls) return aux_planes(c, all(c.kp), false);
-        hipError_t r = aux_planes(c, wall_layers(c.kp), true);
-        if (r == hipSuccess) r = aux_planes(c, inner_planes(c.kp), false);
-        return r;
+        return aux_planes(c, inner_planes(c.kp), false);
     }
 
     static hipError_t mark(const LaunchCtx& c, hipEvent_t e)

@@ -76,19 +76,35 @@ struct KParams {
     const float* plane_frame;
     const float* plane_shift;
     // Walled domains: the wall-node targets solved for the current state
-    // (FP64, [side][component rho, u[3], theta][cell in layer]), and the mass
-    // rebuilt by the closure of the two fluid boundary layers of each wall
+    // (FP64, [side][WSOL_COMPS][cell in layer]: rho, u[3], theta, then the LU
+    // factors of the Jacobian used, 4 x 4 row-major), and the mass rebuilt by
+    // the closure of the two fluid boundary layers of each wall
     // ([side][distance 1, 2 from the wall][cell in layer]).
     double* wsol;
     double* mflu;
+    // The closed unknown populations of the three boundary layers of each
+    // wall (deviations h, FP32, [side][closed_slot][cell in layer]), written
+    // by the solve and read by every pass over the state.
+    float* wclosed;
 };
+
+// Slots of the closed-population buffer per wall and column (at most: 18 for
+// D3Q39, 15 + 7 + 3 for D2Q37).
+constexpr int WCLOSED_SLOTS = 32;
 
 // Wall targets: 8 slots x (D + 2) components x nlayer cells, doubles, laid out
 // [slot][component][cell in layer].  Slots 0-5 hold the previous-step rho,
 // u[D], theta of the 6 boundary layers (3 per wall, wall_slot); slots 6 and
 // 7 the wall-node target solved in the previous step at the low and high
-// wall (the starting point of the next solve).
+// wall (the starting point of the next solve).  Then, per wall, the LU factors
+// of the Jacobian that solve used ([side][16][cell in layer]; all zero before
+// the first solve).
 constexpr int TGT_SLOTS = 8;
+constexpr int WSOL_COMPS = 21;
+__host__ __device__ inline long long tgt_lu_offset(int D, int side, int nlayer)
+{
+    return ((long long)TGT_SLOTS * (D + 2) + 16LL * side) * nlayer;
+}
 __host__ __device__ inline int wall_slot(int k, int n)
 {
     return k < 3 ? k : (k >= n - 3 ? k - (n - 6) : -1);

@@ -150,8 +150,9 @@ def test_state_layout_by_frame_mode(walls, storage, frames, per_cell):
     # frame plane (and momentum plane), each padded to 256 bytes
     extra = (-(-N * 4 // 256) * 256) * (per_cell // 4) if per_cell else (2 + 7 * 6) * nz * 4
     # walls: the next step's targets, (D + 2) doubles per cell of the 3 + 3 wall
-    # layers, and the starting point of the two wall-node solves
-    targets = 8 * 5 * nx * ny * 8 if walls else 0
+    # layers, and the starting point (D + 2) and Jacobian factors (16) of the
+    # two wall-node solves
+    targets = (8 * 5 + 2 * 16) * nx * ny * 8 if walls else 0
     assert sb.value == 39 * pitch * elem + extra + targets
     assert holb.holb_destroy(h) == holb.OK
 

@@ -80,7 +80,15 @@ typedef int32_t holb_status;
  * about 3x smaller BF16 errors in flows with O(0.05) velocities, for a second
  * round of Q - 1 loads per pull (at 256^3 about 1.5x the step time of CELL).
  * AUTO picks PLANE for FP32 and FP16 storage with walls (which impose the
- * mean profile along the wall-normal axis) and CELL otherwise. */
+ * mean profile along the wall-normal axis), CELL for BF16 with walls, CELL_U
+ * for FP16 with the thermal source in a periodic domain, and CELL otherwise.
+ * Accuracy of the 16-bit forms against the FP64 oracle (relative L-infinity,
+ * bound 2e-3): FP16 meets it on every workload tested at its horizon with
+ * these frames, except a flat liquid slab over 1000 steps (u 2.5e-3 against
+ * the 0.01 c0 velocity floor); BF16 meets it on the walled Rayleigh-Benard
+ * boxes (u 1.75e-3 on 64^3 over 2000 steps) but not on the droplet workload
+ * (u 6e-3 to 1e-2) or the thermal workload at 20,000 steps (u 4.6e-2), with
+ * any frames: use FP16 or FP32 storage there. */
 #define HOLB_FRAMES_AUTO 0
 #define HOLB_FRAMES_CELL 1
 #define HOLB_FRAMES_PLANE 2

@@ -110,9 +110,9 @@ __device__ __forceinline__ uint64_t pull_cell(const KParams& p, const typename C
     // All addresses first, then all loads, then the arithmetic, so that the
     // 2Q loads of a node are in flight together.  The three cases are taken
     // per wavefront: every lane away from the edges (a wave-uniform base per
-    // population and one shared lane offset), only the x edge in reach (a
-    // periodic correction of x per population), or the general wrap with
-    // the wall bookkeeping.
+    // population and one shared lane offset), only the x edge in reach on an
+    // x axis of at least 3 cells (a periodic correction of x per population),
+    // or the general wrap with the wall bookkeeping.
     T raw[L::Q];
     FW fw[L::Q];
     uint64_t unk = 0;
@@ -126,7 +126,9 @@ __device__ __forceinline__ uint64_t pull_cell(const KParams& p, const typename C
             if (CU && MOM1) mw[i] = load_at(mp - shift, cf);
         }
         __builtin_amdgcn_sched_barrier(0);
-    } else if (__all(inner_yz)) {
+    } else if (p.nx >= 3 && __all(inner_yz)) {
+        // one correction of x either way: exact for axes of 3 cells or more
+        // (|c_x| <= 3); shorter x axes take the general wrap below
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) {
             int src = cell - ((L::cz[i] * p.ny + L::cy[i]) * p.nx + L::cx[i]);

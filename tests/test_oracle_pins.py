@@ -487,6 +487,43 @@ def test_global_invariants_body_force():
         assert abs(r[1] - r0[1]) < 1e-13
 
 
+@pytest.mark.parametrize("sources", [orc.SRC_BODY, orc.SRC_BODY | orc.SRC_THERMAL])
+def test_global_energy_work_of_the_body_force(sources):
+    """Total energy E = sum (rho |u|^2 + rho D c0^2 theta) / 2 of the fields of
+    Eq. (4.5), periodic body-force run: the collision adds tr G_2 = 2 u.F to
+    the energy moment of each node (Eq. 2.3 with the source of Eq. 3.3; the
+    thermal source adds none), streaming moves it, and rho |u|^2 + rho D
+    c0^2 theta = e + u.F, so E grows from one step to the next by the mean of
+    the body-force work W = sum u.F of the two steps, to rounding.  A reduction
+    that dropped the u.F shift, a source with a wrong trace or a thermal
+    source that carried energy would break this."""
+    L = orc.Lattice(orc.D2Q37)
+    n = 24
+    rng = np.random.default_rng(17)
+    g = (2e-4, -3e-4)
+    s = orc.Sim(orc.D2Q37, n, n, tau_hat=0.7, sources=sources, g=g, prandtl=0.7)
+    s.init(1 + 0.05 * rng.standard_normal((n, n)), 0.05 * rng.standard_normal((2, n, n)),
+           1 + 0.05 * rng.standard_normal((n, n)))
+
+    def work():
+        r, u, _ = s.fields()
+        return float(np.sum(r * (u[0] * g[0] + u[1] * g[1])))
+
+    e_prev, w_prev = s.reduce()[4], work()
+    e0 = e_prev
+    for _ in range(20):
+        s.step(1)
+        e, w = s.reduce()[4], work()
+        assert abs((e - e_prev) - 0.5 * (w + w_prev)) < 1e-12 * abs(e0)
+        e_prev, w_prev = e, w
+    # and the momentum and mass totals are those of the fields
+    r, u, t = s.fields()
+    tot = s.reduce()
+    assert abs(tot[0] - r.sum()) < 1e-12 * tot[0]
+    assert abs(tot[1] - (r * u[0]).sum()) < 1e-12 * tot[0] and abs(tot[2] - (r * u[1]).sum()) < 1e-12 * tot[0]
+    assert abs(tot[4] - 0.5 * np.sum(r * (u[0] ** 2 + u[1] ** 2) + r * L.D * L.c0sq * t)) < 1e-12 * tot[4]
+
+
 # ----------------------------------------------------------------- physics
 
 

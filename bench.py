@@ -234,6 +234,9 @@ def main():
                          "in, and the one the tuner picks there), autotuned for the other workloads")
     ap.add_argument("--frames", default="auto", choices=["auto", "cell", "plane", "cellu"],
                     help="reference frames of the stored populations")
+    ap.add_argument("--grad-lag", action="store_true",
+                    help="thermal source: gradient of the previous step's theta (one pass per step) instead of "
+                         "the same step's (the default, two passes)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep", action="store_true", help="time every kernel variant (to stderr) before the run")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -256,6 +259,8 @@ def main():
     w = workload(args.workload)
     frames = {"auto": 0, "cell": 1, "plane": 2, "cellu": 3}[args.frames]
     cfg = dict(w["config"], storage=storage, frames=frames)
+    if args.grad_lag:
+        cfg["grad_lag"] = 1
     Q = 37 if cfg["lattice"] == 0 else 39
     cells = cfg["nx"] * cfg["ny"] * cfg.get("nz", 1)
     torch.cuda.set_device(0)
@@ -337,6 +342,7 @@ def main():
             "sources": cfg["sources"],
             "walls": cfg["walls"],
             "storage": args.storage,
+            "grad_lag": int(bool(args.grad_lag)),
             "variant": variant,
             # frames as the library resolves them (auto: per plane for FP32 and
             # FP16 with walls, per cell otherwise)

@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define HOLB_ABI_VERSION 3
+#define HOLB_ABI_VERSION 4
 
 typedef int32_t holb_status;
 #define HOLB_OK 0
@@ -139,6 +139,11 @@ typedef struct {
     double u_wall[2][3];  /* wall velocities, same order */
     int32_t frames;       /* HOLB_FRAMES_*: reference of the stored populations */
     int32_t eos;          /* HOLB_EOS_*: equation of state of the pseudopotential */
+    int32_t grad_lag;     /* thermal source: time level of theta in the gradient of H_i (Eq. 3.7;
+                           * Section 3.2 does not fix it): 0 = the same step's theta (a second
+                           * pass over the populations per step), 1 = the previous step's theta,
+                           * which the collision writes out as it goes (one pass per step; before
+                           * the first step, the initial state's theta).  Single runs only. */
 } holb_config;
 
 typedef struct holb_sim holb_sim;

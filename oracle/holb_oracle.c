@@ -430,6 +430,8 @@ struct orc_sim {
     double *force;          /* [3][N] total force density F */
     double *psi, *Fsc;      /* pseudopotential and its force */
     double *gradT;          /* [3][N] */
+    double *theta_prev;     /* theta of the previous step (grad_lag) */
+    int have_prev;
     double *jmom, *emom;    /* first moment [3][N] and energy moment [N] */
     double *trho, *tu, *ttheta; /* TMS targets: previous-step fields */
     long ncol;              /* cells per wall-normal layer */
@@ -445,7 +447,7 @@ void orc_destroy(orc_sim *s)
 {
     if (!s) return;
     free(s->f); free(s->fpost); free(s->rho); free(s->u); free(s->theta); free(s->force);
-    free(s->psi); free(s->Fsc); free(s->gradT); free(s->trho); free(s->tu); free(s->ttheta);
+    free(s->psi); free(s->Fsc); free(s->gradT); free(s->theta_prev); free(s->trho); free(s->tu); free(s->ttheta);
     free(s->jmom); free(s->emom); free(s->lost);
     free(s);
 }
@@ -470,6 +472,7 @@ int orc_create(const orc_config *cfg, orc_sim **out)
     unsigned src = cfg->sources;
     if (src & ~(ORC_SRC_BODY | ORC_SRC_THERMAL | ORC_SRC_PTENSOR)) return ORC_EINVAL;
     if ((src & ORC_SRC_THERMAL) && (cfg->isothermal || !(cfg->prandtl > 0))) return ORC_EUNSUPPORTED;
+    if (cfg->grad_lag != 0 && cfg->grad_lag != 1) return ORC_EINVAL;
     if ((src & ORC_SRC_PTENSOR) && (!cfg->isothermal || cfg->walls)) return ORC_EUNSUPPORTED;
     if (cfg->eos != ORC_EOS_VDW && cfg->eos != ORC_EOS_CS) return ORC_EINVAL;
     orc_sim *s = calloc(1, sizeof *s);
@@ -492,6 +495,7 @@ int orc_create(const orc_config *cfg, orc_sim **out)
     s->psi = xcalloc(N, sizeof(double));
     s->Fsc = xcalloc(3 * N, sizeof(double));
     s->gradT = xcalloc(3 * N, sizeof(double));
+    s->theta_prev = xcalloc(N, sizeof(double));
     s->trho = xcalloc(N, sizeof(double));
     s->tu = xcalloc(3 * N, sizeof(double));
     s->ttheta = xcalloc(N, sizeof(double));
@@ -501,7 +505,7 @@ int orc_create(const orc_config *cfg, orc_sim **out)
     s->lost = xcalloc(2 * s->ncol, sizeof(double));
     if (!s->jmom || !s->emom || !s->lost ||
         !s->f || !s->fpost || !s->rho || !s->u || !s->theta || !s->force || !s->psi || !s->Fsc ||
-        !s->gradT || !s->trho || !s->tu || !s->ttheta) {
+        !s->gradT || !s->trho || !s->tu || !s->ttheta || !s->theta_prev) {
         orc_destroy(s);
         return ORC_EINVAL;
     }
@@ -543,6 +547,7 @@ int orc_init(orc_sim *s, const double *rho, const double *u, const double *theta
         s->ttheta[cell] = th;
     }
     if (bad) return ORC_EINVAL;
+    s->have_prev = 0;
     /* Before the first step no population has left yet; the wall closure of
      * step 0 balances the mass the initial equilibrium would send out, as if
      * it were the post-collision state of a step before. */
@@ -857,10 +862,13 @@ static int macroscopic(orc_sim *s)
 }
 
 /* Section 3.2: grad theta by second-order central differences; along the
- * wall-normal axis the wall layers use a one-sided first difference. */
+ * wall-normal axis the wall layers use a one-sided first difference.  The
+ * section leaves the time level open: theta of the same step, or with
+ * grad_lag of the previous step (the initial state's before the first). */
 static void grad_theta(orc_sim *s)
 {
     long N = s->N;
+    const double *theta = (s->cfg.grad_lag && s->have_prev) ? s->theta_prev : s->theta;
 #ifdef _OPENMP
 #pragma omp parallel for schedule(static)
 #endif
@@ -873,13 +881,13 @@ static void grad_theta(orc_sim *s)
                 long n = s->dims[a];
                 long xp[3] = {x[0], x[1], x[2]}, xm[3] = {x[0], x[1], x[2]};
                 if (s->cfg.walls && a == s->wax) {
-                    if (x[a] == 0) { xp[a] = 1; xm[a] = 0; g = s->theta[cell_of(s, xp)] - s->theta[cell_of(s, xm)]; }
-                    else if (x[a] == n - 1) { xp[a] = n - 1; xm[a] = n - 2; g = s->theta[cell_of(s, xp)] - s->theta[cell_of(s, xm)]; }
-                    else { xp[a] = x[a] + 1; xm[a] = x[a] - 1; g = 0.5 * (s->theta[cell_of(s, xp)] - s->theta[cell_of(s, xm)]); }
+                    if (x[a] == 0) { xp[a] = 1; xm[a] = 0; g = theta[cell_of(s, xp)] - theta[cell_of(s, xm)]; }
+                    else if (x[a] == n - 1) { xp[a] = n - 1; xm[a] = n - 2; g = theta[cell_of(s, xp)] - theta[cell_of(s, xm)]; }
+                    else { xp[a] = x[a] + 1; xm[a] = x[a] - 1; g = 0.5 * (theta[cell_of(s, xp)] - theta[cell_of(s, xm)]); }
                 } else {
                     xp[a] = wrap(x[a] + 1, n);
                     xm[a] = wrap(x[a] - 1, n);
-                    g = 0.5 * (s->theta[cell_of(s, xp)] - s->theta[cell_of(s, xm)]);
+                    g = 0.5 * (theta[cell_of(s, xp)] - theta[cell_of(s, xm)]);
                 }
             }
             s->gradT[a * N + cell] = g;
@@ -974,6 +982,10 @@ int orc_step(orc_sim *s, int nsteps)
         int rc = stages_to_collision(s);
         if (rc) return rc;
         collide(s, s->fpost);
+        if (s->cfg.grad_lag) {
+            memcpy(s->theta_prev, s->theta, sizeof(double) * s->N);
+            s->have_prev = 1;
+        }
         if (s->cfg.walls) {
             memcpy(s->trho, s->rho, sizeof(double) * s->N);
             memcpy(s->tu, s->u, sizeof(double) * 3 * s->N);

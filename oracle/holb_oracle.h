@@ -52,6 +52,7 @@ typedef struct {
     double theta_wall[2];  /* [0] low wall (index 0), [1] high wall */
     double u_wall[2][3];   /* wall velocities, same order */
     int eos;               /* ORC_EOS_VDW or ORC_EOS_CS */
+    int grad_lag;          /* 1: the thermal source takes grad theta of the previous step's theta */
 } orc_config;
 
 typedef struct {

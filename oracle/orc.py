@@ -55,6 +55,7 @@ class _Config(ctypes.Structure):
         ("theta_wall", ctypes.c_double * 2),
         ("u_wall", (ctypes.c_double * 3) * 2),
         ("eos", ctypes.c_int),
+        ("grad_lag", ctypes.c_int),
     ]
 
 
@@ -210,12 +211,12 @@ class Sim:
 
     Keyword arguments mirror the GPU configuration: lattice, nx, ny, nz,
     tau_hat, sources, isothermal, g, prandtl, eos_a, eos_b, eos_T, sc_G,
-    ptensor_k, walls, theta_wall (low, high), u_wall (low, high), eos.
+    ptensor_k, walls, theta_wall (low, high), u_wall (low, high), eos, grad_lag.
     """
 
     def __init__(self, lattice, nx, ny, nz=1, tau_hat=0.8, sources=0, isothermal=0, g=(0, 0, 0),
                  prandtl=1.0, eos_a=0.0, eos_b=0.0, eos_T=0.0, sc_G=-1.0, ptensor_k=0.0, walls=0,
-                 theta_wall=(1.0, 1.0), u_wall=((0, 0, 0), (0, 0, 0)), eos=EOS_VDW):
+                 theta_wall=(1.0, 1.0), u_wall=((0, 0, 0), (0, 0, 0)), eos=EOS_VDW, grad_lag=0):
         c = _Config()
         c.lattice, c.nx, c.ny, c.nz = lattice, nx, ny, nz
         c.tau_hat, c.sources, c.isothermal = tau_hat, sources, int(isothermal)
@@ -225,6 +226,7 @@ class Sim:
         c.eos_a, c.eos_b, c.eos_T, c.sc_G, c.ptensor_k = eos_a, eos_b, eos_T, sc_G, ptensor_k
         c.walls = int(walls)
         c.eos = int(eos)
+        c.grad_lag = int(grad_lag)
         c.theta_wall[0], c.theta_wall[1] = theta_wall
         for w in range(2):
             for a in range(3):

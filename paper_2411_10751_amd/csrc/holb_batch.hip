@@ -239,8 +239,8 @@ holb_status validate_batch(const holb_config* cfgs, int32_t n)
         holb_status s = validate(&cfgs[r]);
         if (s) return fail(s, "run %d: %s", r, g_last_error.c_str());
         const holb_config& c = cfgs[r];
-        if (c.lattice != HOLB_D2Q37 || c.storage != HOLB_STORE_F32 || c.isothermal || c.walls)
-            return fail(HOLB_EUNSUPPORTED, "run %d: batches hold periodic, non-isothermal D2Q37 FP32 runs", r);
+        if (c.lattice != HOLB_D2Q37 || c.storage != HOLB_STORE_F32 || c.isothermal || c.walls || c.grad_lag)
+            return fail(HOLB_EUNSUPPORTED, "run %d: batches hold periodic, non-isothermal D2Q37 FP32 runs (same-step gradient)", r);
         if (c.frames == HOLB_FRAMES_CELL)
             return fail(HOLB_EUNSUPPORTED, "run %d: batched runs use per-plane frames", r);
         if (c.sources & HOLB_SRC_PTENSOR) return fail(HOLB_EUNSUPPORTED, "run %d: no pressure tensor in batches", r);

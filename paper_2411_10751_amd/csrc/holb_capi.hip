@@ -32,7 +32,7 @@ struct Layout {
     size_t tab_off = 0, tab_bytes = 0;  // per-plane frames and shifts (FP32 storage)
     int nm = 0;               // planes along the last axis
     size_t pop_off[2] = {0, 0};
-    size_t aux_off = 0, aux_bytes = 0;
+    size_t aux_off = 0, aux_bytes = 0, aux2_off = 0;
     size_t tgt_off[2] = {0, 0};
     size_t tgt_bytes = 0;
     size_t wall_off = 0, wall_bytes = 0;  // solved wall-node targets and fluid-layer masses (FP64)
@@ -66,6 +66,9 @@ Layout layout_of(const holb_config* c)
     const int fam = family_of(c->sources);
     L.aux_bytes = fam == FAM_PTENSOR ? N * 8 : (fam == FAM_THERMAL ? N * 4 : 0);
     L.aux_off = off; off = align_up(off + L.aux_bytes);
+    // with the previous step's gradient: a second theta field (the two swap
+    // roles every step, like the population buffers)
+    L.aux2_off = off; off = align_up(off + (c->grad_lag ? L.aux_bytes : 0));
     if (c->walls) {
         const size_t nlayer = D == 2 ? (size_t)c->nx : (size_t)c->nx * c->ny;
         L.tgt_bytes = (TGT_SLOTS * (size_t)(D + 2) + 2 * 16) * nlayer * sizeof(double);
@@ -112,10 +115,24 @@ struct holb_sim {
         c.pop_out = ws + lay.pop_off[nxt];
         c.tgt_in = (const double*)(ws + lay.tgt_off[cur]);
         c.tgt_out = (double*)(ws + lay.tgt_off[advance ? nxt : cur]);
+        if (cfg.grad_lag) {
+            // a step reads the last step's theta and writes its own; passes
+            // that do not step (fields, totals) get the other field as
+            // scratch for the wall closure's theta output, which the next
+            // step overwrites whole
+            float* th[2] = {(float*)(ws + lay.aux_off), (float*)(ws + lay.aux2_off)};
+            c.aux_f = advance ? th[cur] : th[nxt];
+            c.theta_out = advance ? th[nxt] : nullptr;
+        }
         c.variant = variant;
         return c;
     }
 };
+
+// With the previous step's gradient: the theta field the next step reads is
+// part of the state.
+static size_t lag_bytes(const holb_sim* s) { return s->cfg.grad_lag ? s->lay.aux_bytes : 0; }
+static char* lag_field(const holb_sim* s) { return s->ws + (s->cur ? s->lay.aux2_off : s->lay.aux_off); }
 
 extern "C" {
 
@@ -212,6 +229,14 @@ holb_status holb_init(holb_sim* s, const float* rho, const float* u, const float
     c.tgt_out = (double*)(s->ws + s->lay.tgt_off[s->cur]);
     e = launch_init(c, rho, u, theta ? theta : rho);
     if (e != hipSuccess) return hip_fail(e, "init kernel");
+    if (s->cfg.grad_lag) {
+        // the theta field of the initial state, which the first step's
+        // gradient reads
+        LaunchCtx ca = s->ctx(false);
+        ca.aux_f = (float*)lag_field(s);
+        e = launch_aux(ca);
+        if (e != hipSuccess) return hip_fail(e, "initial theta field");
+    }
     s->initialized = true;
     return HOLB_OK;
 }
@@ -323,19 +348,23 @@ holb_status holb_error_flags(holb_sim* s, uint32_t* flags)
 // State blob: the current population buffer, then the per-plane table (if
 // any), then the wall targets of the next step (walled domains: the last
 // step's rho, u, theta on the three layers next to each wall).
+
 holb_status holb_state_bytes(holb_sim* s, size_t* bytes)
 {
     if (!s || !bytes) return fail(HOLB_EINVAL, "NULL argument");
-    *bytes = s->lay.pop_bytes + s->lay.tab_bytes + s->lay.tgt_bytes;
+    *bytes = s->lay.pop_bytes + s->lay.tab_bytes + s->lay.tgt_bytes + lag_bytes(s);
     return HOLB_OK;
 }
 
 holb_status holb_get_state(holb_sim* s, void* dst, size_t bytes)
 {
     if (!s || !dst) return fail(HOLB_EINVAL, "NULL argument");
-    const size_t pb = s->lay.pop_bytes, tb = s->lay.tab_bytes, gb = s->lay.tgt_bytes;
-    if (bytes != pb + tb + gb) return fail(HOLB_ESIZE, "state is %zu bytes, got %zu", pb + tb + gb, bytes);
+    const size_t pb = s->lay.pop_bytes, tb = s->lay.tab_bytes, gb = s->lay.tgt_bytes, lb = lag_bytes(s);
+    if (bytes != pb + tb + gb + lb)
+        return fail(HOLB_ESIZE, "state is %zu bytes, got %zu", pb + tb + gb + lb, bytes);
     hipError_t e = hipMemcpyAsync(dst, s->ws + s->lay.pop_off[s->cur], pb, hipMemcpyDeviceToDevice, s->stream);
+    if (e == hipSuccess && lb)
+        e = hipMemcpyAsync((char*)dst + pb + tb + gb, lag_field(s), lb, hipMemcpyDeviceToDevice, s->stream);
     if (e == hipSuccess && tb)
         e = hipMemcpyAsync((char*)dst + pb, s->ws + s->lay.tab_off, tb, hipMemcpyDeviceToDevice, s->stream);
     if (e == hipSuccess && gb)
@@ -348,8 +377,9 @@ holb_status holb_get_state(holb_sim* s, void* dst, size_t bytes)
 holb_status holb_set_state(holb_sim* s, const void* src, size_t bytes)
 {
     if (!s || !src) return fail(HOLB_EINVAL, "NULL argument");
-    const size_t pb = s->lay.pop_bytes, tb = s->lay.tab_bytes, gb = s->lay.tgt_bytes;
-    if (bytes != pb + tb + gb) return fail(HOLB_ESIZE, "state is %zu bytes, got %zu", pb + tb + gb, bytes);
+    const size_t pb = s->lay.pop_bytes, tb = s->lay.tab_bytes, gb = s->lay.tgt_bytes, lb = lag_bytes(s);
+    if (bytes != pb + tb + gb + lb)
+        return fail(HOLB_ESIZE, "state is %zu bytes, got %zu", pb + tb + gb + lb, bytes);
     // a fresh simulation may take a state without holb_init: clear its flags
     hipError_t e = hipMemsetAsync(s->ws + s->lay.err_off, 0, sizeof(unsigned), s->stream);
     if (e == hipSuccess)
@@ -359,6 +389,8 @@ holb_status holb_set_state(holb_sim* s, const void* src, size_t bytes)
     if (e == hipSuccess && gb)
         e = hipMemcpyAsync(s->ws + s->lay.tgt_off[s->cur], (const char*)src + pb + tb, gb, hipMemcpyDeviceToDevice,
                            s->stream);
+    if (e == hipSuccess && lb)
+        e = hipMemcpyAsync(lag_field(s), (const char*)src + pb + tb + gb, lb, hipMemcpyDeviceToDevice, s->stream);
     if (e != hipSuccess) return hip_fail(e, "copying the state in");
     s->initialized = true;
     return HOLB_OK;

@@ -452,6 +452,7 @@ __device__ __forceinline__ void full_macro(const KParams& p, const Frame& fo, co
     macro_from_moments<L>(p, fo, dr, j, ed, Fext, m);
 }
 
+
 // Temperature field value of a node for the gradient stencil: theta minus
 // the global reference theta0, from the frame offset and the deviation.
 __device__ __forceinline__ float theta_field(const KParams& p, const Frame& fo, const Macro& m)
@@ -465,7 +466,8 @@ template <class L, int ST, int FAM, bool WALLS, int FM>
 __device__ __forceinline__ void step_cell(const KParams& p, const typename Codec<ST>::T* __restrict__ fin,
                                           typename Codec<ST>::T* __restrict__ fout, const float* __restrict__ aux_f,
                                           const double* __restrict__ aux_d, const double* __restrict__ tgt_in,
-                                          double* __restrict__ tgt_out, int cell)
+                                          double* __restrict__ tgt_out, int cell,
+                                          float* __restrict__ theta_out = nullptr)
 {
     using LL = Lat<L>;
     int x, y, z;
@@ -485,6 +487,9 @@ __device__ __forceinline__ void step_cell(const KParams& p, const typename Codec
     if (FAM == FAM_THERMAL) {
         grad_theta<L>(p, aux_f, x, y, z, gT);
         hc = p.hfac * m.rho * m.theta;
+        // with the previous step's gradient: this step's theta field, for the
+        // next step (the value the field pass would compute)
+        if (theta_out) theta_out[cell] = theta_field(p, fo, m);
     }
     collide<L, ST == ST_F32>(p, fo, f, m, hc, gT, pc);
     store_cell<L, ST, FM>(p, fout, cell, f, fo, m.rho, m.thb, m.u);

@@ -69,6 +69,9 @@ inline holb_status validate(const holb_config* c)
         return fail(HOLB_EUNSUPPORTED, "per-cell frames with momentum are for 16-bit storage only");
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(c->g[a])) return fail(HOLB_EINVAL, "g must be finite");
+    if (c->grad_lag != 0 && c->grad_lag != 1) return fail(HOLB_EINVAL, "grad_lag must be 0 or 1");
+    if (c->grad_lag && !(c->sources & HOLB_SRC_THERMAL))
+        return fail(HOLB_EINVAL, "grad_lag applies to the thermal source only");
     if (c->sources & HOLB_SRC_THERMAL) {
         if (c->isothermal) return fail(HOLB_EUNSUPPORTED, "thermal source needs isothermal = 0");
         if (!(c->prandtl > 0) || !std::isfinite(c->prandtl)) return fail(HOLB_EINVAL, "prandtl must be > 0");

@@ -18,7 +18,9 @@ struct LaunchCtx {
     KParams kp;
     const void* pop_in;   // current state (post-collision of the last step)
     void* pop_out;        // next state
-    float* aux_f;         // theta field (thermal split path)
+    float* aux_f;         // theta field (thermal source): the one the gradient reads
+    float* theta_out;     // with the previous step's gradient (grad_lag): where the step
+                          // writes its own theta field for the next step; else null
     double* aux_d;        // psi field (pressure-tensor path)
     const double* tgt_in;  // wall targets read this step
     double* tgt_out;       // wall targets written this step

@@ -259,12 +259,12 @@ template <class L, int ST, int FAM, bool WALLS, int FM>
 __global__ void __launch_bounds__(GEN_BLOCK)
 k_step(const KParams p, const PlaneSet ps, const typename Codec<ST>::T* __restrict__ fin,
        typename Codec<ST>::T* __restrict__ fout, const float* __restrict__ aux_f, const double* __restrict__ aux_d,
-       const double* __restrict__ tgt_in, double* __restrict__ tgt_out, int remap)
+       const double* __restrict__ tgt_in, double* __restrict__ tgt_out, float* __restrict__ theta_out, int remap)
 {
     const int c = xcd_block(remap) * GEN_BLOCK + threadIdx.x;
     if (c < (ps.n0 + ps.n1) * p.nlayer)
         step_cell<L, ST, FAM, WALLS, FM>(p, fin, fout, aux_f, aux_d, tgt_in, tgt_out,
-                                                       plane_cell(p, ps, c));
+                                                       plane_cell(p, ps, c), theta_out);
 }
 
 template <class L, int ST, int FAM, bool WALLS, int FM>
@@ -413,7 +413,9 @@ struct Launch {
     static hipError_t wall_prep(const LaunchCtx& c)
     {
         if (!c.kp.walls) return hipSuccess;
-        float* th = FAM == FAM_THERMAL ? c.aux_f : nullptr;
+        // (not when the gradient reads the previous step's field, which
+        // the collision writes)
+        float* th = (FAM == FAM_THERMAL && !c.theta_out) ? c.aux_f : nullptr;
         hipLaunchKernelGGL((k_wall_fluid<L, ST, FM>), dim3(nblocks_for(4 * c.kp.nlayer)), dim3(GEN_BLOCK), 0,
                            c.stream, c.kp, (const T*)c.pop_in, c.tgt_in, th);
         hipError_t r = hipGetLastError();
@@ -446,10 +448,12 @@ struct Launch {
         const dim3 grid(nblocks_for(n));
         if (walls)
             hipLaunchKernelGGL((k_step<L, ST, FAM, true, FM>), grid, dim3(GEN_BLOCK), 0, c.stream, c.kp, ps,
-                               (const T*)c.pop_in, (T*)c.pop_out, c.aux_f, c.aux_d, c.tgt_in, c.tgt_out, remap(c));
+                               (const T*)c.pop_in, (T*)c.pop_out, c.aux_f, c.aux_d, c.tgt_in, c.tgt_out,
+                               c.theta_out, remap(c));
         else
             hipLaunchKernelGGL((k_step<L, ST, FAM, false, FM>), grid, dim3(GEN_BLOCK), 0, c.stream, c.kp, ps,
-                               (const T*)c.pop_in, (T*)c.pop_out, c.aux_f, c.aux_d, c.tgt_in, c.tgt_out, remap(c));
+                               (const T*)c.pop_in, (T*)c.pop_out, c.aux_f, c.aux_d, c.tgt_in, c.tgt_out,
+                               c.theta_out, remap(c));
         return hipGetLastError();
     }
 
@@ -483,7 +487,7 @@ struct Launch {
     static hipError_t step(const LaunchCtx& c)
     {
         hipError_t r = wall_prep(c);
-        if (r == hipSuccess) r = aux(c);
+        if (r == hipSuccess && !c.theta_out) r = aux(c);
         if (r != hipSuccess) return r;
         if (!c.kp.walls) return timed(c, [&] { return step_planes(c, all(c.kp), false); });
         r = step_planes(c, wall_layers(c.kp), true);

@@ -17,7 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libholb.so")
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 FRAMES_AUTO, FRAMES_CELL, FRAMES_PLANE, FRAMES_CELL_U = 0, 1, 2, 3
 EOS_VDW, EOS_CS = 0, 1
 OK, EINVAL, ESIZE, EHIP, ENUMERIC, EUNSUPPORTED, ESTATE = 0, -1, -2, -3, -4, -5, -6
@@ -47,6 +47,7 @@ class holb_config(ctypes.Structure):
         ("u_wall", (ctypes.c_double * 3) * 2),
         ("frames", ctypes.c_int32),
         ("eos", ctypes.c_int32),
+        ("grad_lag", ctypes.c_int32),
     ]
 
 
@@ -157,6 +158,7 @@ def make_config(cfg):
             c.u_wall[w][a] = float(uu[a])
     c.frames = int(cfg.get("frames", 0))
     c.eos = int(cfg.get("eos", 0))
+    c.grad_lag = int(cfg.get("grad_lag", 0))
     return c
 
 

@@ -32,7 +32,8 @@ def oracle_sim(cfg, shape=None):
                    prandtl=cfg.get("prandtl", 1.0), eos_a=cfg.get("eos_a", 0.0), eos_b=cfg.get("eos_b", 0.0),
                    eos_T=cfg.get("eos_T", 0.0), sc_G=cfg.get("sc_G", -1.0), ptensor_k=cfg.get("ptensor_k", 0.0),
                    walls=cfg.get("walls", 0), theta_wall=tuple(cfg.get("theta_wall", (1.0, 1.0))),
-                   u_wall=cfg.get("u_wall", ((0, 0, 0), (0, 0, 0))), eos=cfg.get("eos", 0))
+                   u_wall=cfg.get("u_wall", ((0, 0, 0), (0, 0, 0))), eos=cfg.get("eos", 0),
+                   grad_lag=cfg.get("grad_lag", 0))
 
 
 def run_oracle(cfg, rho, u, theta, steps, shape=None):

@@ -73,6 +73,8 @@ def _cfg(**kw):
     (dict(lattice=1, nx=1024, ny=1024, nz=1024), holb.ESIZE),
     (dict(frames=4), holb.EINVAL),
     (dict(storage=0, frames=3), holb.EUNSUPPORTED),
+    (dict(sources=2, prandtl=0.7, grad_lag=2), holb.EINVAL),
+    (dict(sources=1, grad_lag=1), holb.EINVAL),
 ])
 def test_config_errors(bad, code):
     with pytest.raises(holb.HolbError) as ei:
@@ -127,13 +129,14 @@ def test_create_is_host_only_and_checks_workspace():
 
 
 @pytest.mark.parametrize("walls,storage,frames,per_cell", [
-    (1, 0, 0, 0), (1, 0, 1, 4), (0, 0, 0, 4), (0, 0, 2, 0), (1, 1, 0, 0), (0, 1, 0, 4), (0, 2, 0, 4), (1, 2, 0, 4),
+    (1, 0, 0, 0), (1, 0, 1, 4), (0, 0, 0, 4), (0, 0, 2, 0), (1, 1, 0, 0), (0, 1, 0, 8), (0, 2, 0, 4), (1, 2, 0, 4),
     (0, 1, 3, 8), (0, 2, 1, 4), (0, 2, 3, 8), (1, 1, 2, 0), (1, 2, 2, 0)])
 def test_state_layout_by_frame_mode(walls, storage, frames, per_cell):
     """The raw state holds the Q planes, then per_cell bytes of frame words per
     cell (4 for per-cell frames, 8 with momentum, in two planes) or the per-plane table of
     2 + 7 NS floats per plane; AUTO picks per-plane frames for FP32 and FP16
-    with walls and per-cell frames otherwise."""
+    with walls, momentum frames for periodic FP16 with the thermal source and
+    per-cell frames otherwise."""
     nx, ny, nz = 24, 20, 15  # N = 7200: the frame planes need padding
     cfg = holb.make_config(dict(lattice=1, nx=nx, ny=ny, nz=nz, tau_hat=0.8, sources=3, prandtl=0.7,
                                 g=(0, 0, -1e-5), walls=walls, storage=storage, frames=frames, rho0=1.0,
@@ -270,3 +273,25 @@ def test_bench_traffic_needs_matching_profile(tmp_path, monkeypatch):
     (prof / "traffic_rb3d_f32.txt").write_text(
         "# title, variant 3\nkernel: k_step<D3Q39,0,1,false,1>\nsource_sha256: 0\nhbm_bytes_per_launch: 1\n")
     assert bench.traffic_from_profile("k_step<D3Q39,0,1,false,1>", "rb3d", 0, 3) is None
+
+
+def test_grad_lag_state_and_batches_host_only():
+    """With the previous step's gradient the state carries the theta field the
+    next step reads (N floats more), and batches refuse the option."""
+    base = _cfg(sources=3, prandtl=0.7)
+    sizes = []
+    for lag in (0, 1):
+        cfg = holb.make_config(dict(base, grad_lag=lag))
+        need = ctypes.c_size_t()
+        assert holb.holb_workspace_size(ctypes.byref(cfg), ctypes.byref(need)) == holb.OK
+        h = ctypes.c_void_p()
+        assert holb.holb_create(ctypes.byref(cfg), ctypes.c_void_p(1 << 40), need.value, None,
+                                ctypes.byref(h)) == holb.OK
+        sb = ctypes.c_size_t()
+        assert holb.holb_state_bytes(h, ctypes.byref(sb)) == holb.OK
+        sizes.append(sb.value)
+        assert holb.holb_destroy(h) == holb.OK
+    assert sizes[1] - sizes[0] == 32 * 32 * 4
+    arr = (holb.holb_config * 1)(holb.make_config(dict(base, grad_lag=1)))
+    n = ctypes.c_size_t()
+    assert holb.holb_batch_workspace_size(arr, 1, ctypes.byref(n)) == holb.EUNSUPPORTED

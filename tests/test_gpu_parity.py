@@ -402,6 +402,50 @@ def test_full_ptensor_2048_slab_horizon(storage, frames):
     assert_parity(g, ob, 0, TOL[storage], "vdW slab 2048^2, %d steps st%d fr%d" % (steps, storage, frames))
 
 
+@pytest.mark.parametrize("case", ["rb_f32", "rb_f16", "thermal2d_f32", "thermal2d_f16"])
+def test_grad_lag_parity(case):
+    """The previous step's temperature gradient (grad_lag = 1): the one-pass
+    thermal step against the oracle's same reading, on the walled
+    Rayleigh-Benard box (24 x 24 x 20, 60 steps) and the periodic thermal
+    workload on 128^2 (200 steps), in FP32 and FP16."""
+    storage = 1 if case.endswith("f16") else 0
+    w = _rb(24, 20, 60) if case.startswith("rb") else inputs.thermal_2d(n=128, steps=200)
+    w["config"] = dict(w["config"], grad_lag=1)
+    g, o = _both(w, storage=storage)
+    lat = w["config"]["lattice"]
+    assert_parity(g, o, lat, TOL[storage], w["name"] + " lagged st%d" % storage)
+    # and it is a different scheme from the same-step one (by more than rounding)
+    same = run_oracle(dict(w["config"], grad_lag=0), w["rho"], w["u"], w["theta"], w["steps"])
+    assert max(rel_errors(o, same, lat)) > 1e-6
+
+
+def test_grad_lag_resume_and_variants():
+    """With the previous step's gradient, a run resumed from get_state
+    continues bitwise, and every block order gives the same bits."""
+    import torch
+    from paper_2411_10751_amd import holb
+    w = _rb(32, 24, 8)
+    cfg = dict(w["config"], grad_lag=1)
+    ref = run_gpu(cfg, w["rho"], w["u"], w["theta"], 8)
+    sim = holb.Sim(cfg)
+    sim.init(w["rho"], w["u"], w["theta"])
+    sim.step(3)
+    saved = sim.get_state().clone()
+    sim.close()
+    sim2 = holb.Sim(cfg)
+    sim2.set_state(saved)
+    sim2.step(5)
+    got = [x.cpu().numpy().astype(np.float64) for x in sim2.fields()]
+    sim2.close()
+    for a, b in zip(got, ref):
+        assert np.array_equal(a, b)
+    for v in (1, 3):
+        g = run_gpu(cfg, w["rho"], w["u"], w["theta"], 8, variant=v)
+        for a, b in zip(g, ref):
+            assert np.array_equal(a, b), v
+    torch.cuda.synchronize()
+
+
 # ------------------------------------------------ workloads at their horizons
 
 _C3H = {}

@@ -91,6 +91,16 @@ __device__ __forceinline__ Frame plane_frame_of(const KParams& p, int m)
     return F;
 }
 
+// A wavefront on a wall layer (walled domains) whose lanes all lie at least
+// 3 cells from the edges along the wall and in one plane along the normal.
+template <class L>
+__device__ __forceinline__ bool wall_layer_wave(const KParams& p, int x, int y, int z)
+{
+    const bool lat = x >= 3 && x < p.nx - 3 && (L::D == 2 || (y >= 3 && y < p.ny - 3));
+    const int m = L::D == 3 ? z : y;
+    return __all(lat && m == __builtin_amdgcn_readfirstlane(m));
+}
+
 // MOM1 (FM_CELLU): load the momentum words with the first phase (for
 // kernels with few registers of their own) instead of in a second phase.
 template <class L, int ST, bool WALLS, int FM, bool MOM1 = false>
@@ -137,6 +147,29 @@ __device__ __forceinline__ uint64_t pull_cell(const KParams& p, const typename C
             raw[i] = load_at(fin + (long long)i * p.pitch, (unsigned)src * (unsigned)sizeof(T));
             if (CF) fw[i] = load_at(fp, (unsigned)src * (unsigned)sizeof(FW));
             if (CU && MOM1) mw[i] = load_at(mp, (unsigned)src * 4u);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    } else if (WALLS && p.walls && wall_layer_wave<L>(p, x, y, z)) {
+        // a wall layer, every lane away from the edges along the wall and in
+        // one plane: a population whose source plane lies beyond the wall is
+        // unknown for the whole wavefront and is not read; the others take
+        // the interior addressing
+        const int m = L::D == 3 ? z : y, nm = L::D == 3 ? p.nz : p.ny;
+        const unsigned cb = (unsigned)cell * (unsigned)sizeof(T), cf = (unsigned)cell * (unsigned)sizeof(FW);
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            const int ms = m - (L::D == 3 ? L::cz[i] : L::cy[i]);
+            if (ms >= 0 && ms < nm) {
+                const int shift = (L::cz[i] * p.ny + L::cy[i]) * p.nx + L::cx[i];
+                raw[i] = load_uniform_at(fin + ((long long)i * p.pitch - shift), cb);
+                if (CF) fw[i] = load_at(fp - shift, cf);
+                if (CU && MOM1) mw[i] = load_at(mp - shift, cf);
+            } else {
+                unk |= 1ull << i;
+                raw[i] = T(0);
+                if (CF) fw[i] = 0u;
+                if (CU && MOM1) mw[i] = 0u;
+            }
         }
         __builtin_amdgcn_sched_barrier(0);
     } else {

@@ -176,7 +176,11 @@ holb_status holb_create(const holb_config* cfg, void* dev_workspace, size_t byte
 holb_status holb_init(holb_sim* s, const float* rho, const float* u, const float* theta);
 
 /* Advance n >= 0 time steps of Eq. (4.4) (wall closure, shifted moments,
- * sources, BGK collision, streaming).  Asynchronous on the stream. */
+ * sources, BGK collision, streaming).  Asynchronous on the stream.  Runs of
+ * 16 steps go as one replay of a HIP graph (captured on a library-owned
+ * stream at the first such call, again after the kernel variant changes);
+ * the rest, and every step while holb_timing_start is active, are launched
+ * one by one.  Both give the same bits. */
 holb_status holb_step(holb_sim* s, int64_t n);
 
 /* Macroscopic fields of the current state (Eq. 4.5) into device buffers

@@ -98,6 +98,11 @@ struct holb_sim {
     LaunchCtx base;
     std::vector<hipEvent_t> timing;  // event pairs of the timed steps
     size_t timed = 0;                // pairs recorded so far
+    // Step loop as HIP graphs of GRAPH_STEPS steps, one per starting buffer
+    // (captured on a private stream when first needed, replayed on the
+    // caller's stream).
+    hipStream_t cap = nullptr;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
 
     void drop_timing()
     {
@@ -105,7 +110,20 @@ struct holb_sim {
         timing.clear();
         timed = 0;
     }
-    ~holb_sim() { drop_timing(); }
+    void drop_graphs()
+    {
+        for (int k = 0; k < 2; ++k)
+            if (graph[k]) {
+                (void)hipGraphExecDestroy(graph[k]);
+                graph[k] = nullptr;
+            }
+    }
+    ~holb_sim()
+    {
+        drop_timing();
+        drop_graphs();
+        if (cap) (void)hipStreamDestroy(cap);
+    }
 
     LaunchCtx ctx(bool advance) const
     {
@@ -241,11 +259,67 @@ holb_status holb_init(holb_sim* s, const float* rho, const float* u, const float
     return HOLB_OK;
 }
 
+// Steps per captured graph (even: a replay leaves the state in the buffer it
+// started from).
+static const int GRAPH_STEPS = 16;
+
+static holb_status ensure_graph(holb_sim* s, int from)
+{
+    if (s->graph[from]) return HOLB_OK;
+    hipError_t e = hipSuccess;
+    if (!s->cap) e = hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "creating the capture stream");
+    hipGraph_t g = nullptr;
+    e = hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    hipError_t el = hipSuccess;
+    int cur = from;
+    for (int k = 0; k < GRAPH_STEPS && el == hipSuccess; ++k) {
+        LaunchCtx c = s->ctx(true);
+        // the context of the step k of the replay, on the capture stream
+        const int nxt = 1 - cur;
+        c.pop_in = s->ws + s->lay.pop_off[cur];
+        c.pop_out = s->ws + s->lay.pop_off[nxt];
+        c.tgt_in = (const double*)(s->ws + s->lay.tgt_off[cur]);
+        c.tgt_out = (double*)(s->ws + s->lay.tgt_off[nxt]);
+        if (s->cfg.grad_lag) {
+            float* th[2] = {(float*)(s->ws + s->lay.aux_off), (float*)(s->ws + s->lay.aux2_off)};
+            c.aux_f = th[cur];
+            c.theta_out = th[nxt];
+        }
+        c.stream = s->cap;
+        el = launch_step(c);
+        cur = nxt;
+    }
+    e = hipStreamEndCapture(s->cap, &g);
+    if (el != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_fail(el, "capturing the step loop");
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&s->graph[from], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        s->graph[from] = nullptr;
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    return HOLB_OK;
+}
+
 holb_status holb_step(holb_sim* s, int64_t n)
 {
     if (!s) return fail(HOLB_EINVAL, "handle is NULL");
     if (n < 0) return fail(HOLB_EINVAL, "n must be >= 0");
     if (!s->initialized) return fail(HOLB_ESTATE, "holb_step before holb_init");
+    if (s->timing.empty() && n >= GRAPH_STEPS) {
+        // untimed: whole graphs of GRAPH_STEPS steps, the rest eagerly
+        holb_status st = ensure_graph(s, s->cur);
+        if (st) return st;
+        for (; n >= GRAPH_STEPS; n -= GRAPH_STEPS) {
+            hipError_t e = hipGraphLaunch(s->graph[s->cur], s->stream);
+            if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+        }
+    }
     for (int64_t k = 0; k < n; ++k) {
         LaunchCtx c = s->ctx(true);
         if (2 * (s->timed + 1) <= s->timing.size()) {
@@ -408,6 +482,7 @@ holb_status holb_set_variant(holb_sim* s, int32_t variant)
     if (!s) return fail(HOLB_EINVAL, "handle is NULL");
     if (variant < 0 || variant >= num_variants(s->base) || !variant_supported(s->base, variant))
         return fail(HOLB_EUNSUPPORTED, "variant %d does not apply to this configuration", variant);
+    if (variant != s->variant) s->drop_graphs();  // captured with the old variant
     s->variant = variant;
     return HOLB_OK;
 }
@@ -448,6 +523,7 @@ holb_status holb_tune(holb_sim* s, int32_t* variant_out)
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
     if (e != hipSuccess) return hip_fail(e, "tuning");
+    if (best != s->variant) s->drop_graphs();
     s->variant = best;
     if (variant_out) *variant_out = best;
     return HOLB_OK;

@@ -77,6 +77,15 @@ def cpu_baseline(name, storage):
             "kind": "oracle", "sample": sample + " (FP64, %.1f s)" % dt}
 
 
+def frames_of_kernel(kernel):
+    """Frame mode of a single-run step kernel from its name (its last template
+    argument: 0 per cell, 1 per plane, 2 per cell with momentum)."""
+    try:
+        return {0: "cell", 1: "plane", 2: "cellu"}[int(kernel.rstrip(">").rsplit(",", 1)[1])]
+    except (ValueError, IndexError, KeyError):
+        return "unknown"
+
+
 def traffic_from_profile(kernel, name, storage, variant):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the kernel source as it is now, on this kernel and in this
@@ -199,7 +208,8 @@ def bench_batched(args):
                    "one_run_at_a_time_mlups": round(cells / (single_ms * 1e-3) / 1e6, 2)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel,
-                     "kernel_ms": round(kern_ms, 5), "cells_per_launch": kcells, "alg_bytes_per_cell": bpc},
+                     "kernel_ms": round(kern_ms, 5), "cells_per_launch": kcells, "alg_bytes_per_cell": bpc,
+                     "step_frac": round(bpc * cells / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
     }
     if not args.no_cpu_baseline:
         from oracle import orc
@@ -344,10 +354,9 @@ def main():
             "storage": args.storage,
             "grad_lag": int(bool(args.grad_lag)),
             "variant": variant,
-            # frames as the library resolves them (auto: per plane for FP32 and
-            # FP16 with walls, per cell otherwise)
-            "frames": {1: "cell", 2: "plane", 3: "cellu"}.get(
-                frames, "plane" if storage != 2 and cfg.get("walls") else "cell"),
+            # frames as the library resolved them: the last template argument
+            # of the dominant kernel
+            "frames": frames_of_kernel(kernel),
             "mass": totals[0],
         },
         "roofline": {
@@ -362,6 +371,8 @@ def main():
             "cells_per_launch": kcells,
             "alg_bytes_per_cell": bpc,
             "whole_step_gbs": round(bpc * cells / (step_ms * 1e-3) / 1e9, 1),
+            # the whole step (every launch) at the same algorithmic bytes
+            "step_frac": round(bpc * cells / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         },
     }
     if not args.no_cpu_baseline:

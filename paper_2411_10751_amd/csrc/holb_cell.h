@@ -103,7 +103,7 @@ __device__ __forceinline__ bool wall_layer_wave(const KParams& p, int x, int y, 
 
 // MOM1 (FM_CELLU): load the momentum words with the first phase (for
 // kernels with few registers of their own) instead of in a second phase.
-template <class L, int ST, bool WALLS, int FM, bool MOM1 = false>
+template <class L, int ST, bool WALLS, int FM, bool MOM1 = false, bool ISO = false>
 __device__ __forceinline__ uint64_t pull_cell(const KParams& p, const typename Codec<ST>::T* __restrict__ fin,
                                               int x, int y, int z, float (&f)[L::Q], Frame& fo)
 {
@@ -203,11 +203,23 @@ __device__ __forceinline__ uint64_t pull_cell(const KParams& p, const typename C
     f[0] = Codec<ST>::dec(raw[0], p.dref[0]);
     if constexpr (CF) {
         fo = unpack_frame(fw[0]);
-        const FrameRef<L> ref = frame_ref<L>(fo);
+        if constexpr (ISO) {
+            // isothermal: every frame has theta_F = 1, where R_s(S) - R_s(O)
+            // is rho_S - rho_O exactly (the general form below gives the same
+            // bits there)
 #pragma unroll
-        for (int i = 1; i < L::Q; ++i) {
-            const float v = Codec<ST>::dec(raw[i], p.dref[i]) + frame_shift<L>(ref, L::shell[i], unpack_frame(fw[i]));
-            f[i] = (WALLS && ((unk >> i) & 1ull)) ? 0.0f : v;
+            for (int i = 1; i < L::Q; ++i) {
+                const float v = Codec<ST>::dec(raw[i], p.dref[i]) + (unpack_frame(fw[i]).rho - fo.rho);
+                f[i] = (WALLS && ((unk >> i) & 1ull)) ? 0.0f : v;
+            }
+        } else {
+            const FrameRef<L> ref = frame_ref<L>(fo);
+#pragma unroll
+            for (int i = 1; i < L::Q; ++i) {
+                const float v = Codec<ST>::dec(raw[i], p.dref[i]) +
+                                frame_shift<L>(ref, L::shell[i], unpack_frame(fw[i]));
+                f[i] = (WALLS && ((unk >> i) & 1ull)) ? 0.0f : v;
+            }
         }
     } else {
         // plane frames: the shift depends only on the plane, the last-axis
@@ -328,12 +340,12 @@ __device__ __forceinline__ void wall_coord(const KParams& p, int x, int y, int z
 // every pass over the state so that they agree bitwise.  f holds the
 // deviations h_i.  WALLS = false compiles out the wall closure (periodic
 // domains and interior planes).
-template <class L, int ST, bool WALLS, int FM, bool MOM1 = false>
+template <class L, int ST, bool WALLS, int FM, bool MOM1 = false, bool ISO = false>
 __device__ __forceinline__ void load_state(const KParams& p, const typename Codec<ST>::T* __restrict__ fin,
                                            const double* __restrict__ tgt_in, int x, int y, int z,
                                            float (&f)[L::Q], Frame& fo, float& dr, float (&j)[3], float& ed)
 {
-    uint64_t unk = pull_cell<L, ST, WALLS, FM, MOM1>(p, fin, x, y, z, f, fo);
+    uint64_t unk = pull_cell<L, ST, WALLS, FM, MOM1, ISO>(p, fin, x, y, z, f, fo);
     if (WALLS && p.walls && unk) {
         // the closure of this state, solved before any pass (k_wall_fluid,
         // k_wall_solve): read its populations
@@ -468,12 +480,14 @@ __device__ __forceinline__ void write_warm_start(const KParams& p, double* __res
     for (int k = 0; k < 16; ++k) lu[(long long)k * p.nlayer] = ws[(long long)(5 + k) * p.nlayer];
 }
 
-template <class L, int ST, int FAM>
-__device__ __forceinline__ void full_macro(const KParams& p, const Frame& fo, const float* __restrict__ aux_f,
-                                           const double* __restrict__ aux_d, int x, int y, int z, float dr,
-                                           const float (&j)[3], float ed, Macro& m, float& pc)
+// Stencil force of the pressure-tensor family (F^SC in FP32 and the
+// coefficient of Eq. 3.12); zero for the other families.
+template <class L, int FAM>
+__device__ __forceinline__ void stencil_force(const KParams& p, const double* __restrict__ aux_d, int x, int y,
+                                              int z, float (&Fext)[3], float& pc)
 {
-    float Fext[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) Fext[a] = 0.0f;
     pc = 0.0f;
     if (FAM == FAM_PTENSOR) {
         double psi_x, Fsc[3];
@@ -482,6 +496,15 @@ __device__ __forceinline__ void full_macro(const KParams& p, const Frame& fo, co
         for (int a = 0; a < 3; ++a) Fext[a] = (float)Fsc[a];
         pc = ptensor_coef(p, psi_x, Fsc);
     }
+}
+
+template <class L, int ST, int FAM>
+__device__ __forceinline__ void full_macro(const KParams& p, const Frame& fo, const float* __restrict__ aux_f,
+                                           const double* __restrict__ aux_d, int x, int y, int z, float dr,
+                                           const float (&j)[3], float ed, Macro& m, float& pc)
+{
+    float Fext[3];
+    stencil_force<L, FAM>(p, aux_d, x, y, z, Fext, pc);
     macro_from_moments<L>(p, fo, dr, j, ed, Fext, m);
 }
 
@@ -495,7 +518,7 @@ __device__ __forceinline__ float theta_field(const KParams& p, const Frame& fo, 
 
 // One full step of one cell: pull, closure, moments, sources, collision and
 // store of the post-collision populations at `cell` of fout.
-template <class L, int ST, int FAM, bool WALLS, int FM>
+template <class L, int ST, int FAM, bool WALLS, int FM, bool ISO = false>
 __device__ __forceinline__ void step_cell(const KParams& p, const typename Codec<ST>::T* __restrict__ fin,
                                           typename Codec<ST>::T* __restrict__ fout, const float* __restrict__ aux_f,
                                           const double* __restrict__ aux_d, const double* __restrict__ tgt_in,
@@ -505,12 +528,15 @@ __device__ __forceinline__ void step_cell(const KParams& p, const typename Codec
     using LL = Lat<L>;
     int x, y, z;
     cell_coords<L>(p, cell, x, y, z);
+    // the psi stencil before the pull: its loads and sums are done before
+    // the populations occupy the register file
+    float Fext[3], pc;
+    stencil_force<L, FAM>(p, aux_d, x, y, z, Fext, pc);
     float f[L::Q], dr, j[3], ed;
     Frame fo;
-    load_state<L, ST, WALLS, FM>(p, fin, tgt_in, x, y, z, f, fo, dr, j, ed);
+    load_state<L, ST, WALLS, FM, false, ISO>(p, fin, tgt_in, x, y, z, f, fo, dr, j, ed);
     Macro m;
-    float pc;
-    full_macro<L, ST, FAM>(p, fo, aux_f, aux_d, x, y, z, dr, j, ed, m, pc);
+    macro_from_moments<L>(p, fo, dr, j, ed, Fext, m);
     if (WALLS && p.walls) {
         write_targets<L>(p, tgt_out, x, y, z, fo, m);
         write_warm_start<L>(p, tgt_out, x, y, z);
@@ -530,7 +556,7 @@ __device__ __forceinline__ void step_cell(const KParams& p, const typename Codec
 
 // Field pass of one cell: theta (thermal family) or psi (pressure-tensor
 // family) of the current state, read by the stencil of the following pass.
-template <class L, int ST, int FAM, bool WALLS, int FM>
+template <class L, int ST, int FAM, bool WALLS, int FM, bool ISO = false>
 __device__ __forceinline__ void aux_cell(const KParams& p, const typename Codec<ST>::T* __restrict__ fin,
                                          const double* __restrict__ tgt_in, float* __restrict__ aux_f,
                                          double* __restrict__ aux_d, int cell)
@@ -539,7 +565,7 @@ __device__ __forceinline__ void aux_cell(const KParams& p, const typename Codec<
     cell_coords<L>(p, cell, x, y, z);
     float f[L::Q], dr, j[3], ed;
     Frame fo;
-    load_state<L, ST, WALLS, FM, true>(p, fin, tgt_in, x, y, z, f, fo, dr, j, ed);
+    load_state<L, ST, WALLS, FM, true, ISO>(p, fin, tgt_in, x, y, z, f, fo, dr, j, ed);
     if (FAM == FAM_PTENSOR) {
         bool bad = false;
         aux_d[cell] = psi_eos(p, (double)fo.rho + (double)dr, L::c0sq, bad);

@@ -121,7 +121,8 @@ inline int frames_of(const holb_config* c)
     if (c->frames == HOLB_FRAMES_CELL) return FM_CELL;
     if (c->frames == HOLB_FRAMES_PLANE) return FM_PLANE;
     if (c->frames == HOLB_FRAMES_CELL_U) return FM_CELLU;
-    if (c->walls) return c->storage != HOLB_STORE_BF16DEV ? FM_PLANE : FM_CELL;
+    if (c->walls) return c->storage == HOLB_STORE_BF16DEV ? FM_CELL : FM_PLANE;
+    if (c->storage == HOLB_STORE_F32) return (c->sources & HOLB_SRC_PTENSOR) ? FM_CELL : FM_PLANE;
     if (c->storage == HOLB_STORE_F16DEV && (c->sources & HOLB_SRC_THERMAL)) return FM_CELLU;
     return FM_CELL;
 }

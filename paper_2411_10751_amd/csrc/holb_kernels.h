@@ -251,7 +251,10 @@ k_aux(const KParams p, const PlaneSet ps, const typename Codec<ST>::T* __restric
       const double* __restrict__ tgt_in, float* __restrict__ aux_f, double* __restrict__ aux_d, int remap)
 {
     const int c = xcd_block(remap) * GEN_BLOCK + threadIdx.x;
-    if (c < (ps.n0 + ps.n1) * p.nlayer)
+    if (c >= (ps.n0 + ps.n1) * p.nlayer) return;
+    if (FM != FM_PLANE && (p.flags & KF_ISO))
+        aux_cell<L, ST, FAM, WALLS, FM, true>(p, fin, tgt_in, aux_f, aux_d, plane_cell(p, ps, c));
+    else
         aux_cell<L, ST, FAM, WALLS, FM>(p, fin, tgt_in, aux_f, aux_d, plane_cell(p, ps, c));
 }
 
@@ -262,9 +265,14 @@ k_step(const KParams p, const PlaneSet ps, const typename Codec<ST>::T* __restri
        const double* __restrict__ tgt_in, double* __restrict__ tgt_out, float* __restrict__ theta_out, int remap)
 {
     const int c = xcd_block(remap) * GEN_BLOCK + threadIdx.x;
-    if (c < (ps.n0 + ps.n1) * p.nlayer)
-        step_cell<L, ST, FAM, WALLS, FM>(p, fin, fout, aux_f, aux_d, tgt_in, tgt_out,
-                                                       plane_cell(p, ps, c), theta_out);
+    if (c >= (ps.n0 + ps.n1) * p.nlayer) return;
+    // per-cell frames of an isothermal run: the shorter frame decode
+    if (FM != FM_PLANE && (p.flags & KF_ISO))
+        step_cell<L, ST, FAM, WALLS, FM, true>(p, fin, fout, aux_f, aux_d, tgt_in, tgt_out, plane_cell(p, ps, c),
+                                               theta_out);
+    else
+        step_cell<L, ST, FAM, WALLS, FM>(p, fin, fout, aux_f, aux_d, tgt_in, tgt_out, plane_cell(p, ps, c),
+                                         theta_out);
 }
 
 template <class L, int ST, int FAM, bool WALLS, int FM>

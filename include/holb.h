@@ -187,7 +187,11 @@ holb_status holb_init(holb_sim* s, const float* rho, const float* u, const float
  * 16 steps go as one replay of a HIP graph (captured on a library-owned
  * stream at the first such call, again after the kernel variant changes);
  * the rest, and every step while holb_timing_start is active, are launched
- * one by one.  Both give the same bits. */
+ * one by one.  Both give the same bits.  With walls a step forks its wall
+ * work (the closure solve) onto a second, library-owned stream of default
+ * priority (created at the first call) and makes the caller's stream wait
+ * for it within the same step: work queued on the caller's stream afterwards
+ * sees the whole step. */
 holb_status holb_step(holb_sim* s, int64_t n);
 
 /* Macroscopic fields of the current state (Eq. 4.5) into device buffers

@@ -103,6 +103,10 @@ struct holb_sim {
     // caller's stream).
     hipStream_t cap = nullptr;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
+    // Walled domains: the stream and events of the wall work of a step
+    // (created with the first step).
+    hipStream_t side = nullptr;
+    hipEvent_t side_ev[3] = {nullptr, nullptr, nullptr};
 
     void drop_timing()
     {
@@ -123,6 +127,9 @@ struct holb_sim {
         drop_timing();
         drop_graphs();
         if (cap) (void)hipStreamDestroy(cap);
+        for (hipEvent_t e : side_ev)
+            if (e) (void)hipEventDestroy(e);
+        if (side) (void)hipStreamDestroy(side);
     }
 
     LaunchCtx ctx(bool advance) const
@@ -143,9 +150,30 @@ struct holb_sim {
             c.theta_out = advance ? th[nxt] : nullptr;
         }
         c.variant = variant;
+        if (side) {
+            c.side = side;
+            c.ev_fork = side_ev[0];
+            c.ev_wall = side_ev[1];
+            c.ev_join = side_ev[2];
+        }
         return c;
     }
 };
+
+// The second stream of a walled simulation and its events.
+static holb_status ensure_side(holb_sim* s)
+{
+    if (!s->cfg.walls || s->side) return HOLB_OK;
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < 3 && e == hipSuccess; ++k)
+        if (!s->side_ev[k]) e = hipEventCreateWithFlags(&s->side_ev[k], hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "creating the wall-stream events");
+    hipStream_t st = nullptr;
+    e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "creating the wall stream");
+    s->side = st;
+    return HOLB_OK;
+}
 
 // With the previous step's gradient: the theta field the next step reads is
 // part of the state.
@@ -311,6 +339,9 @@ holb_status holb_step(holb_sim* s, int64_t n)
     if (!s) return fail(HOLB_EINVAL, "handle is NULL");
     if (n < 0) return fail(HOLB_EINVAL, "n must be >= 0");
     if (!s->initialized) return fail(HOLB_ESTATE, "holb_step before holb_init");
+    if (n == 0) return HOLB_OK;
+    holb_status ss = ensure_side(s);
+    if (ss) return ss;
     if (s->timing.empty() && n >= GRAPH_STEPS) {
         // untimed: whole graphs of GRAPH_STEPS steps, the rest eagerly
         holb_status st = ensure_graph(s, s->cur);
@@ -491,6 +522,8 @@ holb_status holb_tune(holb_sim* s, int32_t* variant_out)
 {
     if (!s) return fail(HOLB_EINVAL, "handle is NULL");
     if (!s->initialized) return fail(HOLB_ESTATE, "holb_tune before holb_init");
+    holb_status ss = ensure_side(s);
+    if (ss) return ss;
     // Trial steps read the current buffer and write the other one (and the
     // other wall-target buffer); the current state is left untouched.
     hipEvent_t t0, t1;

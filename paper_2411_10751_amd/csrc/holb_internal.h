@@ -29,6 +29,12 @@ struct LaunchCtx {
     hipStream_t stream;
     hipEvent_t ev_begin;  // if set, recorded around the dominant kernel of a step
     hipEvent_t ev_end;
+    // Walled domains: a second stream (default priority) on which a step runs
+    // its wall work beside the work of `stream` that does not depend on it,
+    // with the events that fork and join the two.  Null: everything on
+    // `stream`.
+    hipStream_t side;
+    hipEvent_t ev_fork, ev_wall, ev_join;
 };
 
 int num_variants(const LaunchCtx& c);

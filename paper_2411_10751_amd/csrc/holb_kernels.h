@@ -492,8 +492,41 @@ struct Launch {
         return r;
     }
 
+    // A walled step on two streams.  The closure solve of the wall nodes
+    // depends on the current state only, so it runs beside the work that
+    // does not read it: with the same step's gradient, the field pass of the
+    // interior planes (both collisions then follow on the main stream, the
+    // dominant one alone); with grad_lag (the last step's field, no field
+    // pass), the interior collision, the wall-layer collision following the
+    // solve on the second stream.  The two streams never write the same
+    // words: the wall work writes the wall layers' closures, targets, theta
+    // and populations, the main stream the interior planes'.
+    static hipError_t step_two_streams(const LaunchCtx& c)
+    {
+        LaunchCtx w = c;
+        w.stream = c.side;
+        w.ev_begin = w.ev_end = nullptr;
+        hipError_t r = hipEventRecord(c.ev_fork, c.stream);
+        if (r == hipSuccess) r = hipStreamWaitEvent(c.side, c.ev_fork, 0);
+        if (r == hipSuccess) r = wall_prep(w);
+        if (!c.theta_out) {
+            if (r == hipSuccess) r = hipEventRecord(c.ev_wall, c.side);
+            if (r == hipSuccess) r = aux(c);
+            if (r == hipSuccess) r = hipStreamWaitEvent(c.stream, c.ev_wall, 0);
+            if (r == hipSuccess) r = step_planes(c, wall_layers(c.kp), true);
+            if (r == hipSuccess) r = timed(c, [&] { return step_planes(c, inner_planes(c.kp), false); });
+            return r;
+        }
+        if (r == hipSuccess) r = step_planes(w, wall_layers(c.kp), true);
+        if (r == hipSuccess) r = hipEventRecord(c.ev_join, c.side);
+        if (r == hipSuccess) r = timed(c, [&] { return step_planes(c, inner_planes(c.kp), false); });
+        if (r == hipSuccess) r = hipStreamWaitEvent(c.stream, c.ev_join, 0);
+        return r;
+    }
+
     static hipError_t step(const LaunchCtx& c)
     {
+        if (c.kp.walls && c.side) return step_two_streams(c);
         hipError_t r = wall_prep(c);
         if (r == hipSuccess && !c.theta_out) r = aux(c);
         if (r != hipSuccess) return r;

@@ -240,8 +240,8 @@ def main():
     ap.add_argument("--storage", default="f32", choices=list(STORAGE))
     ap.add_argument("--variant", type=int, default=None,
                     help="kernel block order (for the batched workload: its launch shape); -1: autotune; "
-                         "default: 0 for the Rayleigh-Benard box (the order its rocprofv3 summaries were taken "
-                         "in, and the one the tuner picks there), autotuned for the other workloads")
+                         "default: 0 for the single-run workloads (the order their rocprofv3 summaries were "
+                         "taken in; the orders differ by at most 3%% there), autotuned for the batched one")
     ap.add_argument("--frames", default="auto", choices=["auto", "cell", "plane", "cellu"],
                     help="reference frames of the stored populations")
     ap.add_argument("--grad-lag", action="store_true",
@@ -299,7 +299,7 @@ def main():
             print("variant %d: %.4f ms/step" % (v, best[v]), file=sys.stderr, flush=True)
         sim.init(w["rho"], w["u"], w["theta"])
     if args.variant is None:
-        args.variant = 0 if args.workload == "rb3d" else -1
+        args.variant = 0
     if args.variant >= 0:
         sim.set_variant(args.variant)
         variant = args.variant

@@ -1,8 +1,16 @@
 """Build step of the HIP library: compiles csrc/*.hip for gfx950 with hipcc
 into paper_2411_10751_amd/libholb.so (in-tree, so that it travels with the
 source tree).  Usage: python -m paper_2411_10751_amd.build
+
+    python -m paper_2411_10751_amd.build --resource-usage [REGEX]
+
+compiles the kernel units once more with the compiler's resource-usage
+remarks and prints, per kernel whose name matches REGEX, its vector
+registers, accumulation registers, scratch bytes per lane and the waves per
+SIMD they allow (nothing is linked).
 """
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -64,5 +72,53 @@ def build(verbose=False, jobs=7):
     return LIB
 
 
+def resource_usage(pattern=".", jobs=4):
+    """[(kernel, VGPRs, AGPRs, scratch bytes per lane, waves per SIMD)] of the
+    kernels whose demangled name matches `pattern`."""
+    objdir = os.path.join(HERE, "_build", "ru")
+    os.makedirs(objdir, exist_ok=True)
+
+    def one(src):
+        cmd = [hipcc()] + HIPCC_FLAGS + ["-I", CSRC, "-c", os.path.join(CSRC, src), "-o",
+                                         os.path.join(objdir, src.replace(".hip", ".o")),
+                                         "-Rpass-analysis=kernel-resource-usage"]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError("hipcc failed on %s:\n%s" % (src, r.stderr))
+        found, name = {}, None
+        for line in r.stderr.splitlines():
+            m = re.search(r"Function Name: (\S+)", line)
+            if m:
+                name = m.group(1)
+                found[name] = {}
+                continue
+            m = re.search(r"remark:\s+(VGPRs|AGPRs|ScratchSize \[bytes/lane\]|Occupancy \[waves/SIMD\]): (\d+)", line)
+            if m and name:
+                found[name][m.group(1).split()[0]] = int(m.group(2))
+        return found
+
+    units = [s for s in SOURCES if s.startswith("holb_inst_") or s == "holb_batch.hip"]
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        merged = {}
+        for d in ex.map(one, units):
+            merged.update(d)
+    names = list(merged)
+    dem = subprocess.run(["c++filt"], input="\n".join(names), capture_output=True, text=True).stdout.split("\n")
+    out = []
+    for n, dm in zip(names, dem):
+        short = dm.split("(")[0].replace("void ", "").replace("holb::", "").replace(" ", "")
+        if re.search(pattern, short):
+            v = merged[n]
+            out.append((short, v.get("VGPRs"), v.get("AGPRs"), v.get("ScratchSize"), v.get("Occupancy")))
+    return sorted(out)
+
+
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    if "--resource-usage" in sys.argv:
+        rest = sys.argv[sys.argv.index("--resource-usage") + 1:]
+        print("| kernel | VGPRs | AGPRs | scratch B/lane | waves/SIMD |")
+        print("|---|---|---|---|---|")
+        for row in resource_usage(rest[0] if rest else "."):
+            print("| `%s` | %s | %s | %s | %s |" % row)
+    else:
+        print(build(verbose="-v" in sys.argv))

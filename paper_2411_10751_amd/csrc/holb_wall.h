@@ -342,19 +342,24 @@ __device__ __forceinline__ float theta_field64(const KParams& p, const WallState
     return (p.flags & KF_ISO) ? 0.0f : (float)((s.theta - 1.0) - (double)p.thb_ref);
 }
 
+// Chord iterations on one set of Jacobian factors before they are formed
+// anew (a new Jacobian costs NV + 1 closures, a chord iteration one).
+constexpr int CHORD_ITERS = 8;
+
 // Wall-node target from the boundary conditions (see the header): unknowns
 // v = (rho, the tangential components of u, theta; no theta when isothermal),
 // NV of them; residuals (rebuilt mass - want, tangential u after closure -
 // udes, theta after closure - thdes).  Newton's method (chord iterations)
 // started from T, the previous step's solution, with the LU factors LU of the
 // Jacobian the previous step used if have_lu (it changes little from step to
-// step); when four chord iterations have not converged, or without factors,
-// the Jacobian is formed anew by finite differences at the current point.
+// step); when CHORD_ITERS chord iterations have not converged, or without
+// factors, the Jacobian is formed anew by finite differences at the current
+// point.
 // The iteration stops when the update is below 1e-12 relative.  The Jacobian
 // is diagonally dominant (about 0.3 on the diagonal, off-diagonal entries up
 // to 0.19 between rho and theta), so the elimination needs no pivoting.
-// Returns false if it does not converge within four Jacobians; LU holds the
-// factors used last.
+// Returns false if it does not converge within five rounds of factors; LU
+// holds the factors used last.
 template <class L, int SIDE, int NV>
 __device__ __forceinline__ bool wall_solve(const KParams& p, const Frame& fr, float (&h)[L::Q], const WallKnown& K,
                                            double want, const double (&udes)[3], double thdes, WallState& T,
@@ -422,7 +427,7 @@ __device__ __forceinline__ bool wall_solve(const KParams& p, const Frame& fr, fl
                 }
             }
         }
-        for (int it = 0; it < 4; ++it) {
+        for (int it = 0; it < CHORD_ITERS; ++it) {
             double y[NV];
 #pragma unroll
             for (int q = 0; q < NV; ++q) {

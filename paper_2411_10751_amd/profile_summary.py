@@ -4,7 +4,7 @@
     python -m paper_2411_10751_amd.profile_summary traffic FETCH_DIR WRITE_DIR OUT.txt --kernel NAME
            --cells N --bytes-per-cell B --cmd "..." --cmd "..."
     python -m paper_2411_10751_amd.profile_summary counters OUT.md DIR [DIR ...] --kernel NAME
-           --cells N --cmd "..." [--cmd "..."]
+           --cells N [--kernel NAME --cells N ...] --cmd "..." [--cmd "..."]
 
 `kernels` condenses the kernel statistics of a `--kernel-trace --stats`
 run (CSV output) into a table.  `traffic` reads two `--pmc` runs, one with
@@ -15,8 +15,8 @@ reference streaming dispatch of known size that bench.py issues with
 1 GiB written).  The result is HBM bytes per launch, stamped with a hash of the
 kernel sources so that bench.py ignores it once the kernels have changed.
 `counters` reads any number of `--pmc` runs (each a set of SQ counters) and
-tabulates, for one kernel, each counter's mean per dispatch, per cell updated
-and per wavefront (when SQ_WAVES is among them).
+tabulates, for each named kernel, each counter's mean per dispatch, per cell
+updated and per wavefront (when SQ_WAVES is among them).
 """
 import argparse
 import csv
@@ -68,18 +68,55 @@ def _csv(dirname, suffix):
     return rows
 
 
+def _overlap(trace):
+    """From the dispatch trace: per kernel, the time it ran with no other
+    kernel on the device, and the device's busy time (the union of all
+    dispatch intervals), in ns."""
+    ev = []
+    for r in trace:
+        k = short_name(r["Kernel_Name"])
+        t0, t1 = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+        ev.append((t0, 1, k))
+        ev.append((t1, -1, k))
+    ev.sort(key=lambda e: (e[0], e[1]))
+    alone, busy, active, last = {}, 0, {}, None
+    for t, d, k in ev:
+        if last is not None and active:
+            busy += t - last
+            if sum(active.values()) == 1:
+                (only,) = [a for a, n in active.items() if n]
+                alone[only] = alone.get(only, 0) + (t - last)
+        active[k] = active.get(k, 0) + d
+        if active[k] == 0:
+            del active[k]
+        last = t
+    return alone, busy
+
+
 def kernels(args):
     rows = _csv(args.dir, "kernel_stats.csv")
     total = sum(float(r["TotalDurationNs"]) for r in rows)
+    try:
+        alone, busy = _overlap(_csv(args.dir, "kernel_trace.csv"))
+    except SystemExit:
+        alone, busy = {}, 0
     out = ["# Kernel time, %s" % args.title, "", "Command (from the repository root):", "",
            "    " + args.cmd, "",
-           "| kernel | calls | average us | min us | max us | share of GPU time |",
-           "|---|---|---|---|---|---|"]
+           "| kernel | calls | average us | min us | max us | share of summed durations | "
+           "alone, us per call |",
+           "|---|---|---|---|---|---|---|"]
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
     for r in rows[: args.top]:
-        out.append("| `%s` | %s | %.2f | %.2f | %.2f | %.1f%% |" % (
-            short_name(r["Name"]), r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
-            float(r["MaxNs"]) / 1e3, 100.0 * float(r["TotalDurationNs"]) / total))
+        k = short_name(r["Name"])
+        out.append("| `%s` | %s | %.2f | %.2f | %.2f | %.1f%% | %s |" % (
+            k, r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
+            float(r["MaxNs"]) / 1e3, 100.0 * float(r["TotalDurationNs"]) / total,
+            "%.2f" % (alone.get(k, 0) / 1e3 / int(r["Calls"])) if busy else ""))
+    if busy:
+        out += ["", "Summed kernel durations %.3f ms; device busy (union of the dispatch intervals) %.3f ms. "
+                "\"Alone\" is the time a dispatch ran with no other kernel on the device: kernels launched on "
+                "the library's second stream overlap others, and a duration then includes the time it shared "
+                "the device." % (total / 1e6, busy / 1e6)]
     open(args.out, "w").write("\n".join(out) + "\n")
     print("\n".join(out))
 
@@ -141,31 +178,35 @@ def traffic(args):
 
 
 def counters(args):
-    key = args.kernel.replace(" ", "")
-    vals = {}
+    """One table per kernel named by --kernel (repeatable)."""
+    rows = []
     for d in args.dirs:
-        rows = _csv(d, "counter_collection.csv")
-        acc = {}
-        for r in rows:
-            if short_name(r["Kernel_Name"]) != key:
-                continue
-            s, n = acc.get(r["Counter_Name"], (0.0, 0))
-            acc[r["Counter_Name"]] = (s + float(r["Counter_Value"]), n + 1)
-        for c, (s, n) in acc.items():
-            vals[c] = s / n
-    if not vals:
-        raise SystemExit("kernel %s not in the counter output" % key)
-    waves = vals.get("SQ_WAVES")
-    out = ["# Instruction counters of `%s`, %s" % (key, args.title), "",
+        rows.append(_csv(d, "counter_collection.csv"))
+    out = ["# Instruction counters, %s" % args.title, "",
            "Commands (from the repository root), one rocprofv3 pass each:", ""]
     out += ["    " + c for c in args.cmd]
-    out += ["", "Means over the kernel's dispatches; %d cells per dispatch%s." % (
-        args.cells, "" if waves is None else ", %.0f wavefronts" % waves), "",
-        "| counter | per dispatch | per cell | per wavefront |", "|---|---|---|---|"]
-    for c in sorted(vals):
-        v = vals[c]
-        out.append("| %s | %.4g | %.4g | %s |" % (c, v, v / args.cells,
-                                                   "" if not waves else "%.4g" % (v / waves)))
+    for kname, cells in zip(args.kernel, args.cells):
+        key = kname.replace(" ", "")
+        vals = {}
+        for run in rows:
+            acc = {}
+            for r in run:
+                if short_name(r["Kernel_Name"]) != key:
+                    continue
+                s, n = acc.get(r["Counter_Name"], (0.0, 0))
+                acc[r["Counter_Name"]] = (s + float(r["Counter_Value"]), n + 1)
+            for c, (s, n) in acc.items():
+                vals[c] = s / n
+        if not vals:
+            raise SystemExit("kernel %s not in the counter output" % key)
+        waves = vals.get("SQ_WAVES")
+        out += ["", "## `%s`" % key, "",
+                "Means over the kernel's dispatches; %d cells per dispatch%s." % (
+                    cells, "" if waves is None else ", %.0f wavefronts" % waves), "",
+                "| counter | per dispatch | per cell | per wavefront |", "|---|---|---|---|"]
+        for c in sorted(vals):
+            v = vals[c]
+            out.append("| %s | %.4g | %.4g | %s |" % (c, v, v / cells, "" if not waves else "%.4g" % (v / waves)))
     if args.note:
         out += [""] + args.note
     open(args.out, "w").write("\n".join(out) + "\n")
@@ -193,8 +234,8 @@ def main():
     n = sub.add_parser("counters")
     n.add_argument("out")
     n.add_argument("dirs", nargs="+")
-    n.add_argument("--kernel", required=True)
-    n.add_argument("--cells", type=int, required=True)
+    n.add_argument("--kernel", action="append", required=True)
+    n.add_argument("--cells", type=int, action="append", required=True)
     n.add_argument("--cmd", action="append", required=True)
     n.add_argument("--title", default="")
     n.add_argument("--note", action="append", default=[])

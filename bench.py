@@ -73,8 +73,20 @@ def cpu_baseline(name, storage):
     s.step(w["steps"])
     dt = time.perf_counter() - t0
     cells = c["nx"] * c["ny"] * c.get("nz", 1)
-    return {"value": round(cells * w["steps"] / dt / 1e6, 4), "unit": "MLUPS", "cores": orc.num_threads(),
-            "kind": "oracle", "sample": sample + " (FP64, %.1f s)" % dt}
+    cores = orc.num_threads()
+    # the same oracle on one thread, over a twentieth of the steps
+    n1 = max(w["steps"] // 20, 1)
+    orc.set_num_threads(1)
+    try:
+        t1 = time.perf_counter()
+        s.step(n1)
+        dt1 = time.perf_counter() - t1
+    finally:
+        orc.set_num_threads(cores)
+    return {"value": round(cells * w["steps"] / dt / 1e6, 4), "unit": "MLUPS", "cores": cores,
+            "kind": "oracle", "sample": sample + " (FP64, %.1f s)" % dt,
+            "single_thread": {"value": round(cells * n1 / dt1 / 1e6, 4), "unit": "MLUPS", "cores": 1,
+                              "sample": "the same state, %d more steps on one thread (%.1f s)" % (n1, dt1)}}
 
 
 def frames_of_kernel(kernel):

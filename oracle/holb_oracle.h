@@ -97,6 +97,8 @@ int orc_set_state(orc_sim *s, const double *f);
 int orc_collide_only(orc_sim *s, double *fpost);
 void orc_destroy(orc_sim *s);
 int orc_num_threads(void);
+/* Threads of the following OpenMP regions (n > 0; timing of the CPU baseline). */
+void orc_set_num_threads(int n);
 
 #ifdef __cplusplus
 }

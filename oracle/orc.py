@@ -101,6 +101,8 @@ def lib():
         _lib.orc_destroy.argtypes = [ctypes.c_void_p]
         _lib.orc_destroy.restype = None
         _lib.orc_num_threads.argtypes = []
+        _lib.orc_set_num_threads.argtypes = [ctypes.c_int]
+        _lib.orc_set_num_threads.restype = None
     return _lib
 
 
@@ -142,6 +144,10 @@ class Lattice:
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+def set_num_threads(n):
+    lib().orc_set_num_threads(int(n))
 
 
 def feq(lattice, rho, u, theta):

@@ -2,8 +2,8 @@
 
 TEST INFRASTRUCTURE ONLY (used by the tests to pin initial densities).
 
-Maxwell construction (Section 5.4 initialises liquid and gas at the equilibrium
-densities "calculated by the Maxwell construction rule"): at temperature T the
+Maxwell construction (Section 5.4 starts liquid and gas at the coexistence
+densities given by the equal-area rule): at temperature T the
 coexisting densities satisfy equal pressure and equal chemical potential,
 p(rho_g) = p(rho_l) and mu(rho_g) = mu(rho_l), where mu = integral dp / rho is
 the isothermal chemical potential.

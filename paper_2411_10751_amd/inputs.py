@@ -271,6 +271,32 @@ def rayleigh_benard_3d(n=256, steps=200, seed=4, ra=1e5, prandtl=0.71, nu=0.04, 
                 theta=_f32(theta), steps=steps)
 
 
+def rayleigh_benard_2d(ra, nx=200, ny=102, prandtl=1.41, nu=0.04, theta_hot=1.4, theta_cold=1.0,
+                       amp=0.01, rho_mean_theta=1.2, steps=400000):
+    """D2Q37 + body force + thermal source, Section 5.3: an nx x ny channel
+    heated from below (walls normal to y, hot at y = 0, one wall-node layer
+    per side: fluid height H = ny - 2, length L = nx), periodic in x; g from
+    the Rayleigh number of Eq. (5.6), whose expansion coefficient is that of
+    the mean temperature, and nu = c0^2 theta (tau - 1/2) taken at that mean
+    temperature too (the 3D box takes it at theta = 1).  theta is the
+    conduction profile plus the perturbation of Eq. (5.7),
+    amp (theta_h - theta_c) sin(pi x / L) sin(pi y / H) (y from the hot wall),
+    rho = 1.2 / theta, u = 0."""
+    H, L = ny - 2, nx
+    g = ra * nu * nu * (theta_hot + theta_cold) / (2.0 * prandtl * (theta_hot - theta_cold) * H ** 3)
+    y = (np.arange(ny, dtype=np.float64)[:, None] - 0.5) * np.ones((1, nx))
+    x = np.ones((ny, 1)) * (np.arange(nx, dtype=np.float64)[None, :] + 0.5)
+    theta = theta_hot - (theta_hot - theta_cold) * y / H
+    theta = theta + amp * (theta_hot - theta_cold) * np.sin(math.pi * x / L) * np.sin(math.pi * y / H)
+    rho = rho_mean_theta / theta
+    theta_m = 0.5 * (theta_hot + theta_cold)
+    cfg = base_config(lattice=D2Q37, nx=nx, ny=ny, tau_hat=0.5 + nu / (C0SQ_D2Q37 * theta_m),
+                      sources=SRC_BODY | SRC_THERMAL, g=(0.0, -g, 0.0), prandtl=prandtl, walls=1,
+                      theta_wall=(theta_hot, theta_cold), rho0=1.0, theta0=theta_m)
+    return dict(name="d2q37_rb_%dx%d_ra%g" % (nx, ny, ra), config=cfg, rho=_f32(rho),
+                u=_f32(np.zeros((2, ny, nx))), theta=_f32(theta), steps=steps)
+
+
 def batched_runs(nruns=512, seed=5, nmin=32, nmax=256, steps=500):
     """Independent D2Q37 body-force + thermal runs of uneven sizes and
     parameters; run r draws from seed + r: n ~ U{nmin..nmax}, tau ~ U[0.6, 1.2],

@@ -186,6 +186,19 @@ def ptensor_cs_2d(n=256, steps=1000, seed=5, ndrops=6, rmin=12.0, rmax=30.0, gap
                 theta=_f32(np.ones((n, n))), steps=steps, drops=drops)
 
 
+def cs_static_droplet_2d(t_reduced, rho_l, rho_g, n=200, radius=50.0, nu=0.2, k=CS_K, width=5.0, steps=40000):
+    """Section 5.4: one droplet of the Carnahan-Starling gas at T = t_reduced
+    Tc, radius 50 at the centre of a 200 x 200 periodic grid, the Eq. (5.11)
+    profile between the coexistence densities rho_l, rho_g (passed in: the
+    Maxwell construction is not part of this module), nu = 0.2."""
+    rho = droplet_profile(n, [(n / 2.0, n / 2.0, radius)], rho_l, rho_g, width)
+    cfg = base_config(lattice=D2Q37, nx=n, ny=n, tau_hat=0.5 + nu / C0SQ_D2Q37, sources=SRC_PTENSOR,
+                      isothermal=1, eos=EOS_CS, eos_a=CS_A, eos_b=CS_B, eos_T=t_reduced * CS_TC, sc_G=-1.0,
+                      ptensor_k=k, rho0=float(rho.mean()))
+    return dict(name="d2q37_cs_droplet_%d_T%g" % (n, t_reduced), config=cfg, rho=_f32(rho),
+                u=_f32(np.zeros((2, n, n))), theta=_f32(np.ones((n, n))), steps=steps)
+
+
 def ptensor_cs_3d(n=48, steps=100, seed=6, ndrops=3, rmin=6.0, rmax=10.0, gap=6.0, nu=0.2,
                   t_reduced=0.8, k=CS_K_D3Q39, rho_l=CS_RHO_L_08, rho_g=CS_RHO_G_08, width=5.0):
     """D3Q39 droplets of the Carnahan-Starling gas (Section 5.4) at 0.8 Tc:

@@ -803,3 +803,33 @@ def test_laplace_law_static_droplet():
     assert sig.std() / sig.mean() < 0.03, res
     slope, icpt = np.polyfit(1 / res[:, 0], res[:, 1], 1)
     assert abs(icpt) < 0.05 * res[:, 1].max(), (slope, icpt)
+
+
+def _flat_interface_d3q39(t_reduced, k, rho_g, rho_l, nz=200, nu=0.2, steps=20000):
+    """The flat-interface test of Section 5.4 on D3Q39: a 1 x 1 x nz periodic
+    column, liquid between nz/4 and 3 nz/4 (Eq. 5.10 along z)."""
+    tau = 0.5 + nu / (2.0 / 3.0)
+    s = orc.Sim(orc.D3Q39, 1, 1, nz, tau_hat=tau, sources=orc.SRC_PTENSOR, isothermal=1, eos_a=inputs.CS_A,
+                eos_b=inputs.CS_B, eos_T=t_reduced * inputs.CS_TC, sc_G=-1.0, ptensor_k=k, eos=orc.EOS_CS)
+    rho = inputs.flat_profile(nz, 1, rho_l, rho_g).reshape(nz, 1, 1)
+    s.init(rho, np.zeros((3,) + rho.shape), np.ones(rho.shape))
+    s.step(steps)
+    r, u, _ = s.fields()
+    return r[0, 0, 0] / rho_g - 1, r[nz // 2, 0, 0] / rho_l - 1, np.abs(u).max()
+
+
+@pytest.mark.parametrize("t_reduced,gas_tol", [(0.8, 2e-4), (0.9, 3e-3)])
+def test_cs_flat_interface_d3q39_k(t_reduced, gas_tol):
+    """Section 5.4 asks for k such that a flat interface keeps the Maxwell
+    densities, and allows that it depends on the equation of state; on D3Q39
+    it depends on the lattice as well.  With k = 2.203 (the D3Q39 droplet
+    workload's value, found by bisection on the gas density at 0.8 Tc) the
+    gas keeps its Maxwell density within 1e-4 at 0.8 Tc (2.4e-3 at 0.9 Tc,
+    where the bisection gives 2.167) and the liquid within 1e-4, while the
+    D2Q37 value 3.02 c0^4 = 1.471 leaves the gas 20% (0.8 Tc) and 5% (0.9
+    Tc) low."""
+    rg, rl = thermo.cs_maxwell(inputs.CS_A, inputs.CS_B, t_reduced * inputs.CS_TC)
+    eg, el, umax = _flat_interface_d3q39(t_reduced, inputs.CS_K_D3Q39, rg, rl)
+    assert abs(eg) < gas_tol and abs(el) < 2e-4 and umax < 1e-4, (eg, el, umax)
+    eg2, _, _ = _flat_interface_d3q39(t_reduced, inputs.CS_K, rg, rl)
+    assert eg2 < -0.03, eg2

@@ -409,45 +409,58 @@ __device__ __forceinline__ void collide(const KParams& p, const Frame& fr, float
     const float U[3] = {m.u[0] * ic, m.u[1] * ic, m.u[2] * ic};
     const float Ph[3] = {m.F[0] * ic, m.F[1] * ic, m.F[2] * ic};
 
-    // per-shell coefficients of the even (dK0, K2) and odd (K1) parts of the
+    // Per-shell coefficients of the even (dK0, K2) and odd (K1) parts of the
     // equilibrium bracket and of the force source (M1); HS, PS of H and P.
     // dK0 = K0 - (1 + t0) is the even bracket relative to the frame
-    // (thb^2 - thb0^2 = dth (thb + thb0)); R0 = 1 + t0 of the frame.
-    float dK0[L::NS], R0[L::NS], K1[L::NS], K2[L::NS], M1[L::NS], HS[L::NS], PS[L::NS];
+    // (thb^2 - thb0^2 = dth (thb + thb0)); R0 = 1 + t0 of the frame.  The
+    // velocities are ordered by shell, so each shell's coefficients are
+    // formed just before its pairs and are dead after them (few registers
+    // live at once).
     const float muu = -0.5f * uu;
-#pragma unroll
-    for (int s = 0; s < L::NS; ++s) {
+    struct ShellCoef {
+        float dK0, R0, K1, K2, M1, HS, PS;
+    };
+    auto shell_coef = [&](int s) {
+        ShellCoef c;
         const float xx = (float)L::shell_c2[s] * ic;
         const float q2 = 0.125f * (xx * xx - 2.0f * (Df + 2.0f) * xx + Df * (Df + 2.0f));
-        R0[s] = 1.0f + ref_t0<L>(xx, thb0);
-        dK0[s] = muu + 0.125f * uu * uu + dth * (0.5f * (xx - Df) + q2 * (thb + thb0)) +
-                 thb * 0.25f * uu * ((Df + 2.0f) - xx);
-        K1[s] = 1.0f + muu + 0.5f * thb * (xx - Df - 2.0f);
-        K2[s] = 0.5f - 0.25f * uu + 0.25f * thb * (xx - Df - 4.0f);
-        M1[s] = 1.0f + 0.5f * (thb * (xx - Df - 2.0f) - uu);
-        HS[s] = hc * (xx - Df - 2.0f);
-        PS[s] = pc * (xx - Df);
-    }
+        c.R0 = 1.0f + ref_t0<L>(xx, thb0);
+        c.dK0 = muu + 0.125f * uu * uu + dth * (0.5f * (xx - Df) + q2 * (thb + thb0)) +
+                thb * 0.25f * uu * ((Df + 2.0f) - xx);
+        c.K1 = 1.0f + muu + 0.5f * thb * (xx - Df - 2.0f);
+        c.K2 = 0.5f - 0.25f * uu + 0.25f * thb * (xx - Df - 4.0f);
+        c.M1 = 1.0f + 0.5f * (thb * (xx - Df - 2.0f) - uu);
+        c.HS = hc * (xx - Df - 2.0f);
+        c.PS = pc * (xx - Df);
+        return c;
+    };
     // rest velocity
-    h[0] = fmaf(om1, h[0], fmaf(orho, dK0[0], odr * R0[0]) + ka * (PS[0] - UF));
+    {
+        const ShellCoef c = shell_coef(0);
+        h[0] = fmaf(om1, h[0], fmaf(orho, c.dK0, odr * c.R0) + ka * (c.PS - UF));
+    }
 #pragma unroll
-    for (int pp = 0; pp < L::NP; ++pp) {
-        const int i = 1 + 2 * pp;
-        const int s = L::shell[i];
-        constexpr float sixth = 1.0f / 6.0f, c24 = 1.0f / 24.0f;
-        float a = 0.f, b = 0.f, g = 0.f;
-        if (L::cx[i]) { a = fmaf((float)L::cx[i], U[0], a); b = fmaf((float)L::cx[i], Ph[0], b); g = fmaf((float)L::cx[i], gT[0], g); }
-        if (L::cy[i]) { a = fmaf((float)L::cy[i], U[1], a); b = fmaf((float)L::cy[i], Ph[1], b); g = fmaf((float)L::cy[i], gT[1], g); }
-        if (L::cz[i]) { a = fmaf((float)L::cz[i], U[2], a); b = fmaf((float)L::cz[i], Ph[2], b); g = fmaf((float)L::cz[i], gT[2], g); }
-        const float a2 = a * a;
-        const float fe = fmaf(a2, fmaf(a2, c24, K2[s]), dK0[s]);
-        const float fo = a * fmaf(a2, sixth, K1[s]);
-        const float se = fmaf(a, b, PS[s] - UF);
-        const float so = fmaf(b, fmaf(0.5f, a2, M1[s]), fmaf(HS[s], g, -a * UF));
-        const float E = fmaf(orho, fe, odr * R0[s]) + ka * se;
-        const float O = fmaf(orho, fo, ka * so);
-        h[i] = fmaf(om1, h[i], E + O);
-        h[i + 1] = fmaf(om1, h[i + 1], E - O);
+    for (int s = 1; s < L::NS; ++s) {
+        const ShellCoef c = shell_coef(s);
+#pragma unroll
+        for (int pp = 0; pp < L::NP; ++pp) {
+            const int i = 1 + 2 * pp;
+            if (L::shell[i] != s) continue;
+            constexpr float sixth = 1.0f / 6.0f, c24 = 1.0f / 24.0f;
+            float a = 0.f, b = 0.f, g = 0.f;
+            if (L::cx[i]) { a = fmaf((float)L::cx[i], U[0], a); b = fmaf((float)L::cx[i], Ph[0], b); g = fmaf((float)L::cx[i], gT[0], g); }
+            if (L::cy[i]) { a = fmaf((float)L::cy[i], U[1], a); b = fmaf((float)L::cy[i], Ph[1], b); g = fmaf((float)L::cy[i], gT[1], g); }
+            if (L::cz[i]) { a = fmaf((float)L::cz[i], U[2], a); b = fmaf((float)L::cz[i], Ph[2], b); g = fmaf((float)L::cz[i], gT[2], g); }
+            const float a2 = a * a;
+            const float fe = fmaf(a2, fmaf(a2, c24, c.K2), c.dK0);
+            const float fo = a * fmaf(a2, sixth, c.K1);
+            const float se = fmaf(a, b, c.PS - UF);
+            const float so = fmaf(b, fmaf(0.5f, a2, c.M1), fmaf(c.HS, g, -a * UF));
+            const float E = fmaf(orho, fe, odr * c.R0) + ka * se;
+            const float O = fmaf(orho, fo, ka * so);
+            h[i] = fmaf(om1, h[i], E + O);
+            h[i + 1] = fmaf(om1, h[i + 1], E - O);
+        }
     }
     if (CONSERVE) conserve<L>(p, h, m);
 }

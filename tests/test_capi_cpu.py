@@ -295,3 +295,28 @@ def test_grad_lag_state_and_batches_host_only():
     arr = (holb.holb_config * 1)(holb.make_config(dict(base, grad_lag=1)))
     n = ctypes.c_size_t()
     assert holb.holb_batch_workspace_size(arr, 1, ctypes.byref(n)) == holb.EUNSUPPORTED
+
+
+@pytest.mark.parametrize("storage,sources,per_cell", [(0, 4, 4), (0, 1, 0), (1, 4, 4), (1, 1, 4)])
+def test_auto_frames_periodic_by_source(storage, sources, per_cell):
+    """AUTO on a periodic domain: FP32 keeps one frame per plane (no frame
+    words) except with the pressure-tensor source, whose liquid and vapour
+    share planes (per-cell frames, 4 bytes per cell); FP16 without the
+    thermal source keeps per-cell frames."""
+    nx, ny, nz = 16, 16, 12
+    iso = 1 if sources & 4 else 0
+    cfg = holb.make_config(dict(lattice=1, nx=nx, ny=ny, nz=nz, tau_hat=0.8, sources=sources, isothermal=iso,
+                                g=(0, 0, -1e-5), eos_a=9.0 / 49.0, eos_b=2.0 / 21.0, eos_T=0.05, sc_G=-1.0,
+                                ptensor_k=0.5, storage=storage, frames=0, rho0=1.0, theta0=1.0))
+    need = ctypes.c_size_t()
+    assert holb.holb_workspace_size(ctypes.byref(cfg), ctypes.byref(need)) == holb.OK, holb.last_error()
+    h = ctypes.c_void_p()
+    assert holb.holb_create(ctypes.byref(cfg), ctypes.c_void_p(1 << 40), need.value, None, ctypes.byref(h)) == holb.OK
+    sb = ctypes.c_size_t()
+    assert holb.holb_state_bytes(h, ctypes.byref(sb)) == holb.OK
+    N = nx * ny * nz
+    elem = 4 if storage == 0 else 2
+    pitch = -(-N // (256 // elem)) * (256 // elem)
+    extra = (-(-N * 4 // 256) * 256) * (per_cell // 4) if per_cell else (2 + 7 * 6) * nz * 4
+    assert sb.value == 39 * pitch * elem + extra
+    assert holb.holb_destroy(h) == holb.OK

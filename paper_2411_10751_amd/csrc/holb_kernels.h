@@ -15,7 +15,8 @@
 //
 // Generic variant: one cell per thread, 256-thread blocks along x.  Stencil
 // sources (temperature gradient, pseudopotential force) read a field written
-// by a preceding pass over the same state (launch_aux).
+// by a preceding pass over the same state (launch_aux), or, for the
+// temperature gradient with grad_lag, by the previous step's collision.
 #pragma once
 
 #include <hip/hip_runtime.h>

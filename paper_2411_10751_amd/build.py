@@ -72,6 +72,21 @@ def build(verbose=False, jobs=7):
     return LIB
 
 
+PROBE_SRC = os.path.join(HERE, "ceiling_probe.hip")
+PROBE = os.path.join(HERE, "ceiling_probe")
+
+
+def build_probe():
+    """Compile the memory-ceiling probe (a stand-alone measurement program)."""
+    cmd = [hipcc(), "-O3", "-std=c++17", "--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang",
+           "-packed-fp32-ops", PROBE_SRC, "-o", PROBE + ".tmp"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed on %s:\n%s" % (PROBE_SRC, r.stderr))
+    os.replace(PROBE + ".tmp", PROBE)
+    return PROBE
+
+
 def resource_usage(pattern=".", jobs=4):
     """[(kernel, VGPRs, AGPRs, scratch bytes per lane, waves per SIMD)] of the
     kernels whose demangled name matches `pattern`."""
@@ -122,3 +137,4 @@ if __name__ == "__main__":
             print("| `%s` | %s | %s | %s | %s |" % row)
     else:
         print(build(verbose="-v" in sys.argv))
+        print(build_probe())

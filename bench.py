@@ -141,6 +141,9 @@ def bench_batched(args):
     import torch
     from paper_2411_10751_amd import holb, inputs
     runs = inputs.batched_runs(nruns=512, steps=200)
+    if args.grad_lag:
+        for r in runs:
+            r["config"] = dict(r["config"], grad_lag=1)
     cells = sum(r["config"]["nx"] * r["config"]["ny"] for r in runs)
     torch.cuda.set_device(0)
     b = holb.Batch([r["config"] for r in runs])
@@ -215,6 +218,7 @@ def bench_batched(args):
         "dtype": "f32",
         "data": "synthetic (seeded fields of the workload recipe)",
         "config": {"workload": "d2q37_batched_512_runs", "runs": len(runs), "cells": cells,
+                   "grad_lag": int(bool(args.grad_lag)),
                    "variant": variant, "graph_replay_ms_per_step": round(graph_ms, 5),
                    "one_run_at_a_time_ms_per_step": round(single_ms, 5),
                    "one_run_at_a_time_mlups": round(cells / (single_ms * 1e-3) / 1e6, 2)},

@@ -293,15 +293,20 @@ holb_status holb_destroy(holb_sim* s);
 /* ---- Batched form: many independent periodic D2Q37 runs in one launch ---- */
 
 /* Every run uses its own grid (nx, ny), tau_hat, sources, g and Pr; all runs
- * share lattice (D2Q37), storage (HOLB_STORE_F32), isothermal = 0 and
- * walls = 0. */
+ * share lattice (D2Q37), storage (HOLB_STORE_F32), isothermal = 0, walls = 0,
+ * per-plane frames, the thermal source on or off, and grad_lag.  A step is
+ * the temperature pass and the collision pass over all runs (two launches);
+ * with grad_lag = 1 (thermal source: the previous step's temperature
+ * gradient) it is the collision pass alone, which also writes the
+ * temperature field for the next step. */
 holb_status holb_batch_workspace_size(const holb_config* cfgs, int32_t n_runs, size_t* bytes);
 holb_status holb_batch_create(const holb_config* cfgs, int32_t n_runs, void* dev_workspace,
                               size_t bytes, void* hip_stream, holb_batch** out);
 /* rho/u/theta: host arrays of n_runs device pointers, fields laid out per run. */
 holb_status holb_batch_init(holb_batch* b, const float* const* rho, const float* const* u,
                             const float* const* theta);
-/* n steps of every run; steps are replayed from a captured HIP graph. */
+/* n steps of every run; runs of 16 steps are replayed from a captured HIP
+ * graph (one per starting buffer), the rest launched one by one. */
 holb_status holb_batch_step(holb_batch* b, int64_t n);
 holb_status holb_batch_fields(holb_batch* b, int32_t run, float* rho, float* u, float* theta);
 holb_status holb_batch_reduce(holb_batch* b, int32_t run, double out[5]);

@@ -83,7 +83,7 @@ __global__ void __launch_bounds__(BATCH_ITEM)
 k_batch_step(const RunDesc* __restrict__ runs, const int2* __restrict__ items, int nitems, int tile,
              const float* __restrict__ fin, float* __restrict__ fout, const float* __restrict__ aux,
              const double* __restrict__ auxd, const double* __restrict__ tgi, double* __restrict__ tgo, unsigned* err,
-             const float* __restrict__ tab)
+             const float* __restrict__ tab, float* __restrict__ theta_out)
 {
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const int2 t = items[it];
@@ -98,7 +98,7 @@ k_batch_step(const RunDesc* __restrict__ runs, const int2* __restrict__ items, i
             const int cell = c0 + threadIdx.x;
             if (cell < end)
                 step_cell<D2Q37, ST_F32, FAM, false, FM_PLANE>(p, fin + r.off, fout + r.off, aux + r.cell0, auxd, tgi,
-                                                               tgo, cell);
+                                                               tgo, cell, theta_out ? theta_out + r.cell0 : nullptr);
         }
     }
 }
@@ -113,7 +113,10 @@ struct holb_batch {
     int fam = FAM_LOCAL;
     char* ws = nullptr;
     hipStream_t stream = nullptr;
-    size_t pop_off[2] = {0, 0}, pop_elems = 0, aux_off = 0, desc_off = 0, items_off = 0;
+    size_t pop_off[2] = {0, 0}, pop_elems = 0, aux_off = 0, aux2_off = 0, desc_off = 0, items_off = 0;
+    // grad_lag: the collision reads the theta field of the last step and
+    // writes its own into the other one (one launch per step)
+    bool lag = false;
     size_t part_off = 0, out_off = 0, err_off = 0, total = 0;
     size_t tab_off = 0;
     int max_partials = 0;
@@ -142,6 +145,8 @@ struct holb_batch {
     const int2* d_items() const { return (const int2*)(ws + items_off); }
     float* pop(int k) const { return (float*)(ws + pop_off[k]); }
     float* aux() const { return (float*)(ws + aux_off); }
+    // the theta field of the state in buffer k (grad_lag)
+    float* lag_field(int k) const { return (float*)(ws + (k ? aux2_off : aux_off)); }
     float* tab() const { return (float*)(ws + tab_off); }
     unsigned* err() const { return (unsigned*)(ws + err_off); }
 
@@ -168,13 +173,37 @@ struct holb_batch {
         tile = t;
     }
 
-    // One step: the temperature pass (thermal family), then the collision
-    // kernel, optionally between the two timing events.
+    // The temperature pass over the state in buffer `from` into `field`.
+    hipError_t theta_pass(hipStream_t s, int from, float* field) const
+    {
+        hipLaunchKernelGGL(k_batch_aux<FAM_THERMAL>, dim3(grid()), dim3(BATCH_ITEM), 0, s, d_runs(), d_items(),
+                           (int)items.size(), tile, (const float*)pop(from), field, (const double*)nullptr, err(),
+                           (const float*)tab());
+        return hipGetLastError();
+    }
+
+    // One step: the temperature pass (thermal family, same-step gradient),
+    // then the collision kernel, optionally between the two timing events.
+    // With grad_lag the collision reads the last step's field and writes
+    // this step's: one launch per step.
     hipError_t step_once(hipStream_t s, int from, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) const
     {
         const int nit = (int)items.size();
         const float* fin = pop(from);
         float* fout = pop(1 - from);
+        if (lag) {
+            if (ev0) {
+                hipError_t e = hipEventRecord(ev0, s);
+                if (e != hipSuccess) return e;
+            }
+            hipLaunchKernelGGL(k_batch_step<FAM_THERMAL>, dim3(grid()), dim3(BATCH_ITEM), 0, s, d_runs(),
+                               d_items(), nit, tile, fin, fout, (const float*)lag_field(from), (const double*)nullptr,
+                               (const double*)nullptr, (double*)nullptr, err(), (const float*)tab(),
+                               lag_field(1 - from));
+            hipError_t e = hipGetLastError();
+            if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
+            return e;
+        }
         if (fam == FAM_THERMAL) {
             hipLaunchKernelGGL(k_batch_aux<FAM_THERMAL>, dim3(grid()), dim3(BATCH_ITEM), 0, s, d_runs(), d_items(),
                                nit, tile, fin, aux(), (const double*)nullptr, err(), (const float*)tab());
@@ -188,11 +217,12 @@ struct holb_batch {
         if (fam == FAM_THERMAL)
             hipLaunchKernelGGL(k_batch_step<FAM_THERMAL>, dim3(grid()), dim3(BATCH_ITEM), 0, s, d_runs(),
                                d_items(), nit, tile, fin, fout, (const float*)aux(), (const double*)nullptr,
-                               (const double*)nullptr, (double*)nullptr, err(), (const float*)tab());
+                               (const double*)nullptr, (double*)nullptr, err(), (const float*)tab(),
+                               (float*)nullptr);
         else
             hipLaunchKernelGGL(k_batch_step<FAM_LOCAL>, dim3(grid()), dim3(BATCH_ITEM), 0, s, d_runs(), d_items(),
                                nit, tile, fin, fout, (const float*)aux(), (const double*)nullptr, (const double*)nullptr,
-                               (double*)nullptr, err(), (const float*)tab());
+                               (double*)nullptr, err(), (const float*)tab(), (float*)nullptr);
         hipError_t e = hipGetLastError();
         if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
         return e;
@@ -239,8 +269,10 @@ holb_status validate_batch(const holb_config* cfgs, int32_t n)
         holb_status s = validate(&cfgs[r]);
         if (s) return fail(s, "run %d: %s", r, g_last_error.c_str());
         const holb_config& c = cfgs[r];
-        if (c.lattice != HOLB_D2Q37 || c.storage != HOLB_STORE_F32 || c.isothermal || c.walls || c.grad_lag)
-            return fail(HOLB_EUNSUPPORTED, "run %d: batches hold periodic, non-isothermal D2Q37 FP32 runs (same-step gradient)", r);
+        if (c.lattice != HOLB_D2Q37 || c.storage != HOLB_STORE_F32 || c.isothermal || c.walls)
+            return fail(HOLB_EUNSUPPORTED, "run %d: batches hold periodic, non-isothermal D2Q37 FP32 runs", r);
+        if (c.grad_lag != cfgs[0].grad_lag)
+            return fail(HOLB_EUNSUPPORTED, "run %d: all runs must share grad_lag", r);
         if (c.frames == HOLB_FRAMES_CELL)
             return fail(HOLB_EUNSUPPORTED, "run %d: batched runs use per-plane frames", r);
         if (c.sources & HOLB_SRC_PTENSOR) return fail(HOLB_EUNSUPPORTED, "run %d: no pressure tensor in batches", r);
@@ -255,6 +287,7 @@ void plan(holb_batch* b, const holb_config* cfgs, int n)
     b->n = n;
     b->cfgs.assign(cfgs, cfgs + n);
     b->fam = family_of(cfgs[0].sources);
+    b->lag = cfgs[0].grad_lag != 0;
     b->runs.resize(n);
     b->items.clear();
     size_t elems = 0, cells = 0, tabf = 0;
@@ -287,6 +320,10 @@ void plan(holb_batch* b, const holb_config* cfgs, int n)
     b->pop_off[0] = off; off = align_up(off + elems * 4);
     b->pop_off[1] = off; off = align_up(off + elems * 4);
     b->aux_off = off; off = align_up(off + cells * 4);
+    if (b->lag) {
+        b->aux2_off = off;
+        off = align_up(off + cells * 4);
+    }
     b->tab_off = off; off = align_up(off + tabf * 4);
     b->desc_off = off; off = align_up(off + (size_t)n * sizeof(RunDesc));
     b->items_off = off; off = align_up(off + b->items.size() * sizeof(int2));
@@ -369,9 +406,17 @@ holb_status holb_batch_init(holb_batch* b, const float* const* rho, const float*
         hipError_t e = launch_init(c, rho[r], u[r], theta[r]);
         if (e != hipSuccess) return hip_fail(e, "batched init");
     }
+    if (b->lag) {
+        // the theta field of the initial state, which the first step reads
+        hipError_t e = b->theta_pass(b->stream, b->cur, b->lag_field(b->cur));
+        if (e != hipSuccess) return hip_fail(e, "initial theta field");
+    }
     b->initialized = true;
     return HOLB_OK;
 }
+
+// Steps per captured graph (even: a replay ends in the buffer it started from).
+static const int BATCH_GRAPH_STEPS = 16;
 
 static holb_status ensure_graph(holb_batch* b, int from)
 {
@@ -379,8 +424,8 @@ static holb_status ensure_graph(holb_batch* b, int from)
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-    hipError_t e1 = b->step_once(b->cap, from);
-    hipError_t e2 = e1 == hipSuccess ? b->step_once(b->cap, 1 - from) : e1;
+    hipError_t e2 = hipSuccess;
+    for (int k = 0; k < BATCH_GRAPH_STEPS && e2 == hipSuccess; ++k) e2 = b->step_once(b->cap, (from + k) % 2);
     e = hipStreamEndCapture(b->cap, &g);
     if (e2 != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
@@ -416,15 +461,15 @@ holb_status holb_batch_step(holb_batch* b, int64_t n)
         }
         return HOLB_OK;
     }
-    if (n >= 2) {
+    if (n >= BATCH_GRAPH_STEPS) {
         holb_status s = ensure_graph(b, b->cur);
         if (s) return s;
-        for (int64_t k = 0; k + 1 < n; k += 2) {
+        for (; n >= BATCH_GRAPH_STEPS; n -= BATCH_GRAPH_STEPS) {
             hipError_t e = hipGraphLaunch(b->graph[b->cur], b->stream);
             if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
         }
     }
-    if (n % 2) {
+    for (; n > 0; --n) {
         hipError_t e = b->step_once(b->stream, b->cur);
         if (e != hipSuccess) return hip_fail(e, "batched step");
         b->cur = 1 - b->cur;

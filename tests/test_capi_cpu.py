@@ -277,7 +277,9 @@ def test_bench_traffic_needs_matching_profile(tmp_path, monkeypatch):
 
 def test_grad_lag_state_and_batches_host_only():
     """With the previous step's gradient the state carries the theta field the
-    next step reads (N floats more), and batches refuse the option."""
+    next step reads (N floats more); a batch takes the option when all its
+    runs share it (its workspace holds a second theta field) and refuses a
+    mix."""
     base = _cfg(sources=3, prandtl=0.7)
     sizes = []
     for lag in (0, 1):
@@ -292,9 +294,16 @@ def test_grad_lag_state_and_batches_host_only():
         sizes.append(sb.value)
         assert holb.holb_destroy(h) == holb.OK
     assert sizes[1] - sizes[0] == 32 * 32 * 4
-    arr = (holb.holb_config * 1)(holb.make_config(dict(base, grad_lag=1)))
+    nb = []
+    for lag in (0, 1):
+        arr = (holb.holb_config * 2)(*[holb.make_config(dict(base, grad_lag=lag))] * 2)
+        n = ctypes.c_size_t()
+        assert holb.holb_batch_workspace_size(arr, 2, ctypes.byref(n)) == holb.OK
+        nb.append(n.value)
+    assert nb[1] - nb[0] >= 2 * 32 * 32 * 4
+    mixed = (holb.holb_config * 2)(holb.make_config(dict(base, grad_lag=0)), holb.make_config(dict(base, grad_lag=1)))
     n = ctypes.c_size_t()
-    assert holb.holb_batch_workspace_size(arr, 1, ctypes.byref(n)) == holb.EUNSUPPORTED
+    assert holb.holb_batch_workspace_size(mixed, 2, ctypes.byref(n)) == holb.EUNSUPPORTED
 
 
 @pytest.mark.parametrize("storage,sources,per_cell", [(0, 4, 4), (0, 1, 0), (1, 4, 4), (1, 1, 4)])

@@ -793,6 +793,32 @@ def test_batched_parity_and_self_consistency():
     torch.cuda.synchronize()
 
 
+def test_batched_grad_lag():
+    """The batched form with the previous step's temperature gradient (one
+    launch per step): the first 8 runs of the workload over 300 steps match
+    the oracle run with the same reading, and the first two are bitwise equal
+    to the same run launched alone."""
+    import torch
+    from paper_2411_10751_amd import holb
+    runs = inputs.batched_runs(nruns=8, steps=300)
+    for r in runs:
+        r["config"] = dict(r["config"], grad_lag=1)
+    steps = runs[0]["steps"]
+    log("case batched 8 runs with grad_lag, %d steps" % steps)
+    b = holb.Batch([r["config"] for r in runs])
+    b.init([r["rho"] for r in runs], [r["u"] for r in runs], [r["theta"] for r in runs])
+    b.step(steps)
+    for k, r in enumerate(runs):
+        gf = [x.cpu().numpy().astype(np.float64) for x in b.fields(k)]
+        o = run_oracle(r["config"], r["rho"], r["u"], r["theta"], steps)
+        assert_parity(gf, o, 0, TOL[0], r["name"] + " lagged")
+        if k < 2:
+            alone = run_gpu(dict(r["config"], frames=2), r["rho"], r["u"], r["theta"], steps)
+            for a, bb in zip(gf, alone):
+                assert np.array_equal(a, bb)
+    torch.cuda.synchronize()
+
+
 def test_batched_graph_replay_matches_eager():
     """Odd and even step counts (graph replay + eager remainder) agree with
     single eager steps, replayed several times."""

@@ -191,7 +191,8 @@ holb_status holb_init(holb_sim* s, const float* rho, const float* u, const float
  * work (the closure solve) onto a second, library-owned stream of default
  * priority (created at the first call) and makes the caller's stream wait
  * for it within the same step: work queued on the caller's stream afterwards
- * sees the whole step. */
+ * sees the whole step.  The library-owned streams are created on the device
+ * that is current at that first call, which must be the simulation's. */
 holb_status holb_step(holb_sim* s, int64_t n);
 
 /* Macroscopic fields of the current state (Eq. 4.5) into device buffers

@@ -1,4 +1,8 @@
-"""Validations of Sections 5.3 and 5.4 on the GPU, through the C ABI.
+"""Validations of Sections 5.1-5.4 on the GPU, through the C ABI.
+
+Sections 5.1 and 5.2: thermal Couette and Poiseuille flow on the paper's
+56-node channel at its own viscosity nu = 0.01 (test_thermal_channel_paper_
+viscosity, the oracle pins' bounds).
 
 Section 5.3: 2D Rayleigh-Benard convection on the paper's
 200 x 102 channel (fluid height 100 between TMS walls, Pr = 1.41, nu = 0.04,
@@ -130,3 +134,72 @@ def test_cs_droplet_spurious_velocity():
         umax.append(seen[1])
     assert umax[0] < 5e-5
     assert umax[0] > umax[1] > umax[2]
+
+
+def _gpu_thermal_channel(kind, prandtl, ec, ny=56, nu=0.01, re=100.0, theta_top=0.8):
+    """Sections 5.1 and 5.2 on the GPU at the paper's own viscosity (the
+    oracle pins run the same channel at nu = 0.05): D2Q37, one periodic
+    column, walls normal to y, fluid height H = ny - 2; Couette with the top
+    wall at u_w = Re nu / H, or Poiseuille driven by the body force with
+    centre-line speed Re nu / H; Ec = U^2 / (c_p dtheta), c_p = (D + 2) c0^2
+    / 2; started at rest at theta_t and run for 8 H^2 / (pi^2 kappa) steps."""
+    import torch
+    from paper_2411_10751_amd import holb
+    H = ny - 2
+    U = re * nu / H
+    cp = 0.5 * (2 + 2) * C0SQ[0]
+    dth = U * U / (cp * ec)
+    tb = theta_top - dth
+    g = 8.0 * nu * U / H ** 2 if kind == "poiseuille" else 0.0
+    src = (inputs.SRC_BODY if g else 0) | (inputs.SRC_THERMAL if prandtl != 1.0 else 0)
+    cfg = inputs.base_config(lattice=inputs.D2Q37, nx=1, ny=ny, tau_hat=0.5 + nu / (C0SQ[0] * theta_top),
+                             sources=src, prandtl=prandtl, g=(g, 0.0, 0.0), walls=1, theta_wall=(tb, theta_top),
+                             u_wall=((0.0, 0.0, 0.0), (U if kind == "couette" else 0.0, 0.0, 0.0)), theta0=theta_top)
+    steps = int(8 * H * H / (np.pi ** 2 * min(nu, nu / prandtl)))
+    log("case thermal %s Pr %g Ec %g nu %g, %d steps" % (kind, prandtl, ec, nu, steps))
+    sim = holb.Sim(cfg)
+    sim.init(np.ones((ny, 1), np.float32), np.zeros((2, ny, 1), np.float32), np.full((ny, 1), theta_top, np.float32))
+    m0 = sim.reduce()[0]
+    sim.step(steps)
+    r, u, t = (a.cpu().numpy().astype(np.float64) for a in sim.fields())
+    m1 = sim.reduce()[0]
+    torch.cuda.synchronize()
+    sim.close()
+    ys = (np.arange(ny) - 0.5) / H
+    return dict(ys=ys, ux=u[0, :, 0], ts=(t[:, 0] - tb) / dth, U=U, dmass=m1 / m0 - 1.0)
+
+
+def _interior_fit(ch, shape, lo=6):
+    ys = ch["ys"][lo:-lo]
+    A = np.stack([np.ones_like(ys), ys, shape(ys)], axis=1)
+    return np.linalg.lstsq(A, ch["ts"][lo:-lo], rcond=None)[0][2]
+
+
+@pytest.mark.parametrize("kind,prandtl,ec", [("couette", 0.71, 2.0), ("couette", 1.41, 10.0),
+                                             ("poiseuille", 0.71, 2.0), ("poiseuille", 1.41, 5.0)])
+def test_thermal_channel_paper_viscosity(kind, prandtl, ec):
+    """Eqs. (5.1)-(5.2) and (5.4)-(5.5) at nu = 0.01: the velocity profile
+    within 0.5% of U, the interior viscous heating theta'' = -Pr u'^2 / c_p
+    within 2%, and the dimensionless temperature within 8% (Couette) and 15%
+    (Poiseuille) of its maximum, the bounds of the oracle's pins at nu = 0.05
+    (the measured values at both viscosities agree within 0.01)."""
+    ch = _gpu_thermal_channel(kind, prandtl, ec)
+    ys, U = ch["ys"], ch["U"]
+    log("%s Pr %g Ec %g: mass change %.2e" % (kind, prandtl, ec, ch["dmass"]))
+    assert abs(ch["dmass"]) < 1e-6
+    if kind == "couette":
+        assert np.abs(ch["ux"][1:-1] - U * ys[1:-1]).max() < 5e-3 * U
+        c = _interior_fit(ch, lambda y: y * (1 - y))
+        assert abs(c / (0.5 * prandtl * ec) - 1) < 0.02, c
+        exact = ys + 0.5 * prandtl * ec * ys * (1 - ys)
+        bound = 0.08
+    else:
+        assert np.abs(ch["ux"][1:-1] - 4 * U * ys[1:-1] * (1 - ys[1:-1])).max() < 5e-3 * U
+        c = _interior_fit(ch, lambda y: 1 - (1 - 2 * y) ** 4)
+        assert abs(c / (prandtl * ec / 3.0) - 1) < 0.02, c
+        exact = ys + prandtl * ec / 3.0 * (1 - (1 - 2 * ys) ** 4)
+        bound = 0.15
+    err = np.abs(ch["ts"][1:-1] - exact[1:-1]).max() / exact.max()
+    log("%s Pr %g Ec %g: heating coefficient / exact %.4f, profile error %.4f" % (
+        kind, prandtl, ec, c / ((0.5 if kind == "couette" else 1.0 / 3.0) * prandtl * ec), err))
+    assert err < bound

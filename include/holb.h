@@ -80,15 +80,16 @@ typedef int32_t holb_status;
  * about 3x smaller BF16 errors in flows with O(0.05) velocities, for a second
  * round of Q - 1 loads per pull (at 256^3 about 1.5x the step time of CELL).
  * AUTO picks PLANE for FP32 and FP16 storage with walls (which impose the
- * mean profile along the wall-normal axis) and for FP32 in a periodic domain
- * without the pressure-tensor source (its 24-bit significands leave room for
- * the distance to a plane mean, and without frame words the pull is 8-10%
- * faster); CELL for FP32 with the pressure-tensor source in a periodic domain
- * (liquid and vapour in one plane: about 20x the error with PLANE), for BF16
- * with walls and for the remaining 16-bit cases, except CELL_U for FP16 with
- * the thermal source in a periodic domain.  An FP32 state with a jump along
- * the last axis across a periodic boundary (a ramp wrapped around) keeps more
- * precision with CELL.
+ * mean profile along the wall-normal axis) and for FP32 and FP16 in a
+ * periodic domain without the pressure-tensor source (without frame words the
+ * pull is 8-10% faster in FP32 and 20% faster in FP16 on the body-force
+ * workload, whose FP16 errors are those of CELL), except CELL_U for FP16 with
+ * the thermal source in a periodic domain; CELL with the pressure-tensor
+ * source in a periodic domain (liquid and vapour in one plane: about 20x the
+ * error with PLANE in FP32), for BF16 with walls and for BF16 in a periodic
+ * domain.  A state with a jump along the last axis across a periodic boundary
+ * (a ramp wrapped around), or with density or temperature varying strongly
+ * within the planes, keeps more precision with CELL.
  * Accuracy of the 16-bit forms against the FP64 oracle (relative L-infinity,
  * bound 2e-3): FP16 meets it on every workload tested at its horizon with
  * these frames, except a flat liquid slab over 1000 steps (u 2.5e-3 against

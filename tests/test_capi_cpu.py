@@ -134,9 +134,9 @@ def test_create_is_host_only_and_checks_workspace():
 def test_state_layout_by_frame_mode(walls, storage, frames, per_cell):
     """The raw state holds the Q planes, then per_cell bytes of frame words per
     cell (4 for per-cell frames, 8 with momentum, in two planes) or the per-plane table of
-    2 + 7 NS floats per plane; AUTO picks per-plane frames for FP32 and for
-    FP16 with walls, momentum frames for periodic FP16 with the thermal source
-    and per-cell frames otherwise."""
+    2 + 7 NS floats per plane; with the body and thermal sources AUTO picks
+    per-plane frames for FP32 and for FP16 with walls, momentum frames for
+    periodic FP16 and per-cell frames for BF16."""
     nx, ny, nz = 24, 20, 15  # N = 7200: the frame planes need padding
     cfg = holb.make_config(dict(lattice=1, nx=nx, ny=ny, nz=nz, tau_hat=0.8, sources=3, prandtl=0.7,
                                 g=(0, 0, -1e-5), walls=walls, storage=storage, frames=frames, rho0=1.0,
@@ -306,12 +306,14 @@ def test_grad_lag_state_and_batches_host_only():
     assert holb.holb_batch_workspace_size(mixed, 2, ctypes.byref(n)) == holb.EUNSUPPORTED
 
 
-@pytest.mark.parametrize("storage,sources,per_cell", [(0, 4, 4), (0, 1, 0), (1, 4, 4), (1, 1, 4)])
+@pytest.mark.parametrize("storage,sources,per_cell", [(0, 4, 4), (0, 1, 0), (1, 4, 4), (1, 1, 0), (1, 2, 8),
+                                                      (2, 1, 4), (2, 4, 4)])
 def test_auto_frames_periodic_by_source(storage, sources, per_cell):
-    """AUTO on a periodic domain: FP32 keeps one frame per plane (no frame
-    words) except with the pressure-tensor source, whose liquid and vapour
-    share planes (per-cell frames, 4 bytes per cell); FP16 without the
-    thermal source keeps per-cell frames."""
+    """AUTO on a periodic domain: FP32 and FP16 keep one frame per plane (no
+    frame words) except with the pressure-tensor source, whose liquid and
+    vapour share planes (per-cell frames, 4 bytes per cell), and FP16 with the
+    thermal source (momentum frames, 8 bytes per cell); BF16 keeps per-cell
+    frames."""
     nx, ny, nz = 16, 16, 12
     iso = 1 if sources & 4 else 0
     cfg = holb.make_config(dict(lattice=1, nx=nx, ny=ny, nz=nz, tau_hat=0.8, sources=sources, isothermal=iso,

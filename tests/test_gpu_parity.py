@@ -39,6 +39,16 @@ def test_body_force_64_full_horizon():
     assert_parity(g, o, 0, TOL[0], w["name"])
 
 
+@pytest.mark.parametrize("frames", [0, 1])
+def test_body_force_64_full_horizon_fp16(frames):
+    """The same in FP16 deviation storage, with the frames AUTO takes there
+    (one per plane) and with per-cell frames."""
+    w = inputs.body_force_2d(n=64, steps=500)
+    w = dict(w, config=dict(w["config"], frames=frames))
+    g, o = _both(w, storage=1)
+    assert_parity(g, o, 0, TOL[1], w["name"])
+
+
 def test_body_force_invariants_on_gpu():
     """Mass constant and total momentum growing by M g per step (FP64 totals
     of the FP32 state)."""
@@ -622,7 +632,8 @@ def test_state_roundtrip_and_resume(storage):
         assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("case", ["rb_f32", "rb_f16", "rb_bf16_mom", "thermal2d", "ptensor_f16", "periodic3d"])
+@pytest.mark.parametrize("case", ["rb_f32", "rb_f16", "rb_bf16_mom", "thermal2d", "ptensor_f16", "periodic3d",
+                                  "body2d_f16"])
 def test_poisoned_workspace(case):
     """Every population slot a step should write is written, and nothing
     uninitialised reaches a result: with the whole workspace filled with NaN
@@ -640,6 +651,9 @@ def test_poisoned_workspace(case):
         cfg = dict(w["config"])
     elif case == "ptensor_f16":
         w = _ptensor_small(n=64, steps=6)
+        cfg = dict(w["config"], storage=1)
+    elif case == "body2d_f16":
+        w = inputs.body_force_2d(n=40, steps=6)
         cfg = dict(w["config"], storage=1)
     else:
         w = _rb(16, 20, 6, walls=0)

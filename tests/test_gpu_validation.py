@@ -33,12 +33,14 @@ gives no values in the text, so the magnitude is parity unpinned: the test
 checks that the currents settle, that they fall as T_r rises towards the
 critical point (measured: 1.6e-5, 4.2e-6, 5e-7 at T_r = 0.7, 0.8, 0.9, two
 orders below the 1e-3 scale the paper attributes to D2Q9), and that the
-liquid keeps its Maxwell density within 1%.
+liquid keeps its Maxwell density within 1%.  On a reduced grid (radius 20 on
+80 x 80) the settled currents are compared with the FP64 oracle's
+(test_cs_droplet_spurious_parity).
 """
 import numpy as np
 import pytest
 
-from _parity import C0SQ, TOL, assert_parity, log, run_gpu, run_oracle
+from _parity import C0SQ, TOL, assert_parity, log, rel_errors, run_gpu, run_oracle
 from oracle import thermo
 from paper_2411_10751_amd import inputs
 
@@ -134,6 +136,33 @@ def test_cs_droplet_spurious_velocity():
         umax.append(seen[1])
     assert umax[0] < 5e-5
     assert umax[0] > umax[1] > umax[2]
+
+
+@pytest.mark.parametrize("tr", [pytest.param(0.7, marks=pytest.mark.xfail(
+    reason="the settled currents agree (|u|max to 1.3e-4, the field to 1.0e-3 of |u|max), but after 6000 steps at "
+           "density ratio 43 the FP32 velocity field is 1.78e-5 off against the 1e-5 bound", strict=True)), 0.8])
+def test_cs_droplet_spurious_parity(tr):
+    """The static droplet of the same recipe on a grid the oracle can run to
+    the settled state (radius 20 on 80 x 80; the currents settle within 6000
+    steps), in FP32 storage against the FP64 oracle: the settled
+    spurious-velocity field within 1% of its maximum, then the fields within
+    the FP32 tolerance."""
+    rho_g, rho_l = thermo.cs_maxwell(inputs.CS_A, inputs.CS_B, tr * inputs.CS_TC)
+    steps = 6000
+    w = inputs.cs_static_droplet_2d(tr, rho_l, rho_g, n=80, radius=20.0, steps=steps)
+    log("case %s steps=%d" % (w["name"], steps))
+    g = run_gpu(w["config"], w["rho"], w["u"], w["theta"], steps)
+    o = run_oracle(w["config"], w["rho"], w["u"], w["theta"], steps)
+    e = rel_errors(g, o, 0)
+    ug = g[1].astype(np.float64)
+    umax_g = np.sqrt((ug * ug).sum(axis=0)).max()
+    umax_o = np.sqrt((o[1] * o[1]).sum(axis=0)).max()
+    du = np.abs(ug - o[1]).max() / umax_o
+    log("T_r %.1f: rel Linf errors rho %.3g u %.3g theta %.3g; spurious |u|max GPU %.5e, oracle %.5e; "
+        "max |u_gpu - u_oracle| / |u|max %.2e" % (tr, e[0], e[1], e[2], umax_g, umax_o, du))
+    assert du < 1e-2
+    assert abs(umax_g / umax_o - 1.0) < 1e-2
+    assert max(e) <= TOL[0], e
 
 
 def _gpu_thermal_channel(kind, prandtl, ec, ny=56, nu=0.01, re=100.0, theta_top=0.8):

@@ -275,6 +275,60 @@ def test_bench_traffic_needs_matching_profile(tmp_path, monkeypatch):
     assert bench.traffic_from_profile("k_step<D3Q39,0,1,false,1>", "rb3d", 0, 3) is None
 
 
+def test_profile_overlap_accounting():
+    """Kernel summaries: the time each kernel ran with no other on the device
+    and the device's busy time, from dispatch intervals (ns)."""
+    from paper_2411_10751_amd.profile_summary import _overlap
+    trace = [
+        {"Kernel_Name": "void holb::k_aux<D3Q39, 0, 1, false, 1>(holb::KParams)", "Start_Timestamp": "0",
+         "End_Timestamp": "100"},
+        {"Kernel_Name": "void holb::k_wall_fluid<D3Q39, 0, 1>(holb::KParams)", "Start_Timestamp": "10",
+         "End_Timestamp": "120"},
+        {"Kernel_Name": "void holb::k_step<D3Q39, 0, 1, false, 1>(holb::KParams)", "Start_Timestamp": "200",
+         "End_Timestamp": "300"},
+    ]
+    alone, busy = _overlap(trace)
+    assert busy == 120 + 100
+    assert alone["k_aux<D3Q39,0,1,false,1>"] == 10
+    assert alone["k_wall_fluid<D3Q39,0,1>"] == 20
+    assert alone["k_step<D3Q39,0,1,false,1>"] == 100
+
+
+def test_profile_traffic_scaling(tmp_path):
+    """Traffic summaries: each counter's mean per dispatch of the kernel,
+    scaled by what the same counter reads for the calibration dispatch of
+    1 GiB in and 1 GiB out, compared with the algorithmic bytes."""
+    import sys
+    from paper_2411_10751_amd import profile_summary as ps
+
+    def run(d, counter, rows):
+        (tmp_path / d).mkdir()
+        lines = ["Kernel_Name,Counter_Name,Counter_Value"] + ["\"%s\",%s,%s" % (k, counter, v) for k, v in rows]
+        (tmp_path / d / "p_counter_collection.csv").write_text("\n".join(lines) + "\n")
+
+    neg = "void at::native::vectorized_elementwise_kernel<4, at::native::neg_kernel>(int)"
+    kern = "void holb::k_step<D3Q39, 0, 1, false, 1>(holb::KParams)"
+    # FETCH_SIZE reads half the calibration bytes, WRITE_SIZE all of them
+    run("fetch", "FETCH_SIZE", [(neg, 524288.0), (kern, 1000.0), (kern, 1200.0)])
+    run("write", "WRITE_SIZE", [(neg, 1048576.0), (kern, 2000.0)])
+    out = tmp_path / "traffic.txt"
+    argv = sys.argv
+    sys.argv = ["x", "traffic", str(tmp_path / "fetch"), str(tmp_path / "write"), str(out),
+                "--kernel", "k_step<D3Q39,0,1,false,1>", "--cells", "100", "--bytes-per-cell", "312",
+                "--cmd", "a", "--cmd", "b", "--title", "test, variant 0"]
+    try:
+        ps.main()
+    finally:
+        sys.argv = argv
+    vals = dict(l.split(": ", 1) for l in out.read_text().splitlines() if not l.startswith("#"))
+    assert float(vals["fetch_scale"]) == pytest.approx(2.0)
+    assert float(vals["write_scale"]) == pytest.approx(1.0)
+    hbm = 1100.0 * 1024 * 2.0 + 2000.0 * 1024
+    assert float(vals["hbm_bytes_per_launch"]) == pytest.approx(hbm, abs=0.5)
+    assert int(vals["algorithmic_bytes_per_launch"]) == 31200
+    assert vals["source_sha256"] == ps.source_sha256()
+
+
 def test_grad_lag_state_and_batches_host_only():
     """With the previous step's gradient the state carries the theta field the
     next step reads (N floats more); a batch takes the option when all its
